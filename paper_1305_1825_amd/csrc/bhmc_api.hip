@@ -1,0 +1,648 @@
+// Host side of the C ABI declared in include/bhmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdarg>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "bhmc.h"
+#include "bhmc_dev.hpp"
+#include "bhmc_internal.hpp"
+
+namespace bhmc {
+
+const EvalOps* eval_ops_p0(); const EvalOps* eval_ops_p1(); const EvalOps* eval_ops_p2();
+const EvalOps* eval_ops_p3(); const EvalOps* eval_ops_p4(); const EvalOps* eval_ops_p5();
+const EvalOps* eval_ops_p6(); const EvalOps* eval_ops_p7(); const EvalOps* eval_ops_p8();
+const EvalOps* eval_ops_p9(); const EvalOps* eval_ops_p10();
+
+const EvalOps* eval_ops(int p) {
+    switch (p) {
+        case 0: return eval_ops_p0(); case 1: return eval_ops_p1(); case 2: return eval_ops_p2();
+        case 3: return eval_ops_p3(); case 4: return eval_ops_p4(); case 5: return eval_ops_p5();
+        case 6: return eval_ops_p6(); case 7: return eval_ops_p7(); case 8: return eval_ops_p8();
+        case 9: return eval_ops_p9(); case 10: return eval_ops_p10();
+        default: return nullptr;
+    }
+}
+
+// ------------------------------------------------------------ utility kernels
+__global__ void k_sweep_prep(Rep* reps, int R, int* queue, const long long* add) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x)
+        reps[r].move_end += add[r];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;
+}
+
+__global__ void k_reset_queue(int* queue) { *queue = 0; }
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated sum of v[0..n) times scale into *out (one workgroup).
+__global__ void __launch_bounds__(1024) k_sum(const double* v, int n, double scale, double* out) {
+    __shared__ double ss[1024], cc[1024];
+    double s = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        double t, e;
+        two_sum(s, v[k], t, e);
+        s = t; c += e;
+    }
+    ss[threadIdx.x] = s; cc[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double t, e;
+            two_sum(ss[threadIdx.x], ss[threadIdx.x + w], t, e);
+            ss[threadIdx.x] = t;
+            cc[threadIdx.x] += cc[threadIdx.x + w] + e;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = scale * (ss[0] + cc[0]);
+}
+
+void launch_sweep_prep(hipStream_t s, Rep* reps, int R, int* queue, const long long* add) {
+    hipLaunchKernelGGL(k_sweep_prep, dim3((R + 255) / 256), dim3(256), 0, s, reps, R, queue, add);
+}
+void launch_reset_queue(hipStream_t s, int* queue) {
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, queue);
+}
+void launch_sum(hipStream_t s, const double* v, int n, double scale, double* out) {
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, s, v, n, scale, out);
+}
+
+}  // namespace bhmc
+
+using bhmc::Rep;
+
+// ------------------------------------------------------------ handle
+struct bhmc_tree {
+    int R = 0, p = 0, nterms = 0, mstride = 0;
+    hipStream_t stream = nullptr;
+    std::vector<bhmc_params> params;
+    std::vector<Rep> host;           // mirror of the descriptor table
+    Rep* reps = nullptr;             // device descriptor table
+    std::vector<void*> arena1, arena2;
+    const bhmc::EvalOps* ops = nullptr;
+    int* queue = nullptr;
+    int* list_all = nullptr;         // replicas, largest first
+    int* list_one = nullptr;         // scratch list of one replica
+    long long* sweep_add = nullptr;  // n_r per replica
+    bhmc::MoveIO* io = nullptr;
+    double* eterm = nullptr; int eterm_n = 0;
+    double* scalar = nullptr;
+    int mc_grid = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t graph_stream = nullptr;  // capture needs a stream other than the null stream
+    uint64_t graph_seed = 0; double graph_step = 0.0; bool graph_ok = false;
+};
+
+static thread_local std::string g_err;
+
+static bhmc_status fail(bhmc_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static bhmc_status fail(bhmc_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? BHMC_ENOMEM : BHMC_EHIP, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                               \
+    } while (0)
+
+extern "C" const char* bhmc_last_error(void) { return g_err.c_str(); }
+
+static bhmc_status check_params(const bhmc_params& P, int64_t n) {
+    if (n < 1 || n > (1 << 22)) return fail(BHMC_EINVAL, "n = %lld out of range [1, 2^22]", (long long)n);
+    if (!(P.theta >= 0.0 && P.theta < 1.0)) return fail(BHMC_EINVAL, "theta must lie in [0, 1)");
+    if (P.p < 0 || P.p > bhmc::kPMax) return fail(BHMC_EINVAL, "p must lie in [0, %d]", bhmc::kPMax);
+    if (P.leaf_cap < 0 || P.n0 < 0) return fail(BHMC_EINVAL, "leaf_cap and n0 must be >= 0");
+    if (P.max_depth < 0 || P.max_depth > bhmc::kMaxDepth) return fail(BHMC_EINVAL, "max_depth must lie in [0, 21]");
+    if (P.slot_slack < 1) return fail(BHMC_EINVAL, "slot_slack must be >= 1");
+    if (!(P.box_side > 0.0) || !std::isfinite(P.box_side)) return fail(BHMC_EINVAL, "box_side must be > 0");
+    if (P.geom != 0 && P.geom != 1) return fail(BHMC_EINVAL, "geom must be 0 or 1");
+    if (P.images && P.geom != 1) return fail(BHMC_EINVAL, "images need the spherical geometry");
+    if (P.geom == 1 && !(P.r_min >= 0.0 && P.r_min < P.r_max)) return fail(BHMC_EINVAL, "need 0 <= r_min < r_max");
+    if (P.images && !(P.a > 0.0 && P.a <= P.r_min && P.eps_in > 0.0 && P.eps_out >= 0.0))
+        return fail(BHMC_EINVAL, "images need 0 < a <= r_min and eps_in > 0");
+    if (!(P.hard_core >= 0.0) || !(P.l_B >= 0.0)) return fail(BHMC_EINVAL, "hard_core and l_B must be >= 0");
+    return BHMC_OK;
+}
+
+static void fill_rep(Rep& r, const bhmc_params& P, int64_t n) {
+    memset(&r, 0, sizeof(Rep));
+    for (int d = 0; d < 3; ++d) { r.lo[d] = P.box_lo[d]; r.hi[d] = P.box_lo[d] + P.box_side; }
+    r.side = P.box_side;
+    r.scale = 2097152.0 / P.box_side;
+    r.theta2 = P.theta * P.theta;
+    r.l_B = P.l_B;
+    r.a = P.a;
+    r.a2 = P.a * P.a;
+    r.gamma = (P.eps_out + P.eps_in) != 0.0 ? (P.eps_out - P.eps_in) / (P.eps_out + P.eps_in) : 0.0;
+    r.Qc = P.geom == 1 ? P.Q_center : 0.0;
+    r.rmin2 = P.r_min * P.r_min;
+    r.rmax2 = P.r_max * P.r_max;
+    r.tau2 = P.hard_core * P.hard_core;
+    r.geom = P.geom; r.images = P.images; r.leaf_cap = P.leaf_cap; r.n0 = P.n0;
+    r.max_depth = P.max_depth; r.slack = P.slot_slack;
+    r.n = (int)n;
+    r.nsrc = P.images ? 2 * (int)n : (int)n;
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Carver {
+    char* base; size_t off = 0;
+    template <class T> T* take(size_t count) {
+        T* p = (T*)(base + off);
+        off = align_up(off + sizeof(T) * (count ? count : 1));
+        return p;
+    }
+};
+
+static size_t phase1_bytes(int nsrc) {
+    size_t b = 0;
+    b += align_up(32 * (size_t)nsrc); b += 2 * align_up(8 * (size_t)nsrc); b += 4 * align_up(4 * (size_t)nsrc);
+    return b;
+}
+
+static bhmc_status alloc_phase1(bhmc_tree* t, int r) {
+    Rep& h = t->host[r];
+    if (t->arena1[r]) { hipFree(t->arena1[r]); t->arena1[r] = nullptr; }
+    HIP_TRY(hipMalloc(&t->arena1[r], phase1_bytes(h.nsrc)));
+    Carver c{(char*)t->arena1[r]};
+    h.src = c.take<double4>(h.nsrc);
+    h.keys = c.take<uint64_t>(h.nsrc); h.ktmp = c.take<uint64_t>(h.nsrc);
+    h.perm = c.take<int>(h.nsrc); h.ptmp = c.take<int>(h.nsrc);
+    h.leaf_of = c.take<int>(h.nsrc); h.slot_of = c.take<int>(h.nsrc);
+    return BHMC_OK;
+}
+
+static bhmc_status alloc_phase2(bhmc_tree* t, int r) {
+    Rep& h = t->host[r];
+    if (t->arena2[r]) { hipFree(t->arena2[r]); t->arena2[r] = nullptr; }
+    const size_t nc = h.ncell, nl = h.nleaf, np = h.pool;
+    size_t b = align_up(32 * nc) + 6 * align_up(4 * nc) + align_up(8 * nc) +
+               align_up(8 * nc * (size_t)t->mstride) + 3 * align_up(4 * nl) + align_up(32 * np) +
+               align_up(4 * np);
+    HIP_TRY(hipMalloc(&t->arena2[r], b));
+    Carver c{(char*)t->arena2[r]};
+    h.cgeo = c.take<double4>(nc);
+    h.clink = c.take<int>(nc); h.ccount = c.take<int>(nc); h.cparent = c.take<int>(nc);
+    h.clevel = c.take<int>(nc); h.cbegin = c.take<int>(nc); h.cend = c.take<int>(nc);
+    h.ckey = c.take<uint64_t>(nc);
+    h.M = c.take<double>(nc * (size_t)t->mstride);
+    h.lcell = c.take<int>(nl); h.lbase = c.take<int>(nl); h.lcap = c.take<int>(nl);
+    h.pool4 = c.take<double4>(np); h.pidx = c.take<int>(np);
+    return BHMC_OK;
+}
+
+static bhmc_status upload(bhmc_tree* t) {
+    HIP_TRY(hipMemcpyAsync(t->reps, t->host.data(), sizeof(Rep) * t->R, hipMemcpyHostToDevice, t->stream));
+    return BHMC_OK;
+}
+static bhmc_status download(bhmc_tree* t) {
+    HIP_TRY(hipMemcpyAsync(t->host.data(), t->reps, sizeof(Rep) * t->R, hipMemcpyDeviceToHost, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    return BHMC_OK;
+}
+
+static const char* status_name(int s) {
+    switch (s) {
+        case -1: return "a non-finite coordinate or charge";
+        case -2: return "an ion outside the confinement, or a source outside the root cube";
+        case -5: return "inconsistent tree sizes";
+        default: return "error";
+    }
+}
+
+// Build (or rebuild) the replicas in `list`.  x == nullptr rebuilds from the
+// replicas' own current ions.
+static bhmc_status build_list(bhmc_tree* t, const std::vector<int>& list, const double* x,
+                              const double* y, const double* z, const double* q,
+                              const std::vector<long long>& ion_off) {
+    const int nr = (int)list.size();
+    int* dlist = nullptr;
+    long long* doff = nullptr;
+    HIP_TRY(hipMalloc(&dlist, sizeof(int) * nr));
+    HIP_TRY(hipMalloc(&doff, sizeof(long long) * nr));
+    struct Guard { int* a; long long* b; ~Guard() { hipFree(a); hipFree(b); } } guard{dlist, doff};
+    HIP_TRY(hipMemcpyAsync(dlist, list.data(), sizeof(int) * nr, hipMemcpyHostToDevice, t->stream));
+    if (x) HIP_TRY(hipMemcpyAsync(doff, ion_off.data(), sizeof(long long) * nr, hipMemcpyHostToDevice, t->stream));
+    for (int r : list)
+        if (!t->host[r].src) { bhmc_status st = alloc_phase1(t, r); if (st) return st; }
+    bhmc_status st = upload(t);
+    if (st) return st;
+    bhmc::launch_sources(t->stream, nr, t->reps, dlist, x, y, z, q, x ? doff : nullptr);
+    bhmc::launch_sort(t->stream, nr, t->reps, dlist);
+    bhmc::launch_count(t->stream, nr, t->reps, dlist);
+    HIP_TRY(hipGetLastError());
+    if ((st = download(t))) return st;
+    for (int r : list) {
+        Rep& h = t->host[r];
+        if (h.status) return fail(h.status == -1 ? BHMC_EINVAL : BHMC_EOUTSIDE, "replica %d: %s", r, status_name(h.status));
+        if (h.ncell >= (1 << 24)) return fail(BHMC_EINVAL, "replica %d: %d cells exceed 2^24", r, h.ncell);
+    }
+    for (int r : list) if ((st = alloc_phase2(t, r))) return st;
+    if ((st = upload(t))) return st;
+    bhmc::launch_topology(t->stream, nr, t->reps, dlist);
+    bhmc::launch_leaves(t->stream, nr, t->reps, dlist);
+    bhmc::launch_moments(t->stream, nr, t->reps, dlist, t->nterms, t->mstride);
+    HIP_TRY(hipGetLastError());
+    if ((st = download(t))) return st;
+    for (int r : list)
+        if (t->host[r].status) return fail(BHMC_EHIP, "replica %d: %s", r, status_name(t->host[r].status));
+    return BHMC_OK;
+}
+
+static void destroy(bhmc_tree* t) {
+    if (!t) return;
+    if (t->gexec) hipGraphExecDestroy(t->gexec);
+    if (t->graph) hipGraphDestroy(t->graph);
+    if (t->graph_stream) hipStreamDestroy(t->graph_stream);
+    for (void* p : t->arena1) if (p) hipFree(p);
+    for (void* p : t->arena2) if (p) hipFree(p);
+    hipFree(t->reps); hipFree(t->queue); hipFree(t->list_all); hipFree(t->list_one);
+    hipFree(t->sweep_add); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar);
+    delete t;
+}
+
+static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n_per, const double* x,
+                          const double* y, const double* z, const double* q, void* stream,
+                          bhmc_tree** out) {
+    if (!out) return fail(BHMC_EINVAL, "out is null");
+    *out = nullptr;
+    if (R < 1 || !params || !n_per) return fail(BHMC_EINVAL, "need R >= 1 replicas");
+    if (!x || !y || !z || !q) return fail(BHMC_EINVAL, "null input array");
+    for (int r = 0; r < R; ++r) {
+        bhmc_status st = check_params(params[r], n_per[r]);
+        if (st) return st;
+        if (params[r].p != params[0].p) return fail(BHMC_EINVAL, "all replicas must share p");
+    }
+    bhmc_tree* t = new bhmc_tree();
+    t->R = R;
+    t->p = params[0].p;
+    t->nterms = bhmc::nterms_of(t->p);
+    t->mstride = bhmc::mstride_of(t->p);
+    t->stream = (hipStream_t)stream;
+    t->params.assign(params, params + R);
+    t->host.resize(R);
+    t->arena1.assign(R, nullptr);
+    t->arena2.assign(R, nullptr);
+    t->ops = bhmc::eval_ops(t->p);
+    std::vector<long long> off(R);
+    long long acc = 0;
+    for (int r = 0; r < R; ++r) { fill_rep(t->host[r], params[r], n_per[r]); off[r] = acc; acc += n_per[r]; }
+    auto bail = [&](bhmc_status st) { destroy(t); return st; };
+    if (hipMalloc(&t->reps, sizeof(Rep) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "descriptor table"));
+    if (hipMalloc(&t->queue, sizeof(int)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "queue"));
+    if (hipMalloc(&t->list_all, sizeof(int) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "list"));
+    if (hipMalloc(&t->list_one, sizeof(int)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "list"));
+    if (hipMalloc(&t->sweep_add, sizeof(long long) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "sweep"));
+    if (hipMalloc(&t->io, sizeof(bhmc::MoveIO)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "io"));
+    if (hipMalloc(&t->scalar, sizeof(double) * 4) != hipSuccess) return bail(fail(BHMC_ENOMEM, "scalar"));
+    bhmc::upload_build_tables(t->p);
+    std::vector<int> list(R);
+    std::iota(list.begin(), list.end(), 0);
+    bhmc_status st = build_list(t, list, x, y, z, q, off);
+    if (st) return bail(st);
+    // largest replica first in the sweep queue
+    std::vector<int> order(R);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_per[a] > n_per[b]; });
+    std::vector<long long> add(n_per, n_per + R);
+    if (hipMemcpy(t->list_all, order.data(), sizeof(int) * R, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->sweep_add, add.data(), sizeof(long long) * R, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(BHMC_EHIP, "upload of the sweep tables failed"));
+    int dev = 0, ncu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    t->mc_grid = std::max(1, std::min(R, ncu > 0 ? ncu : 256));
+    *out = t;
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_build(const bhmc_params* params, int64_t n, const double* x, const double* y,
+                                  const double* z, const double* q, void* hip_stream, bhmc_tree** out) {
+    return create(params, 1, &n, x, y, z, q, hip_stream, out);
+}
+
+extern "C" bhmc_status bhmc_batch_create(const bhmc_params* params, int32_t R, const int64_t* n_per_replica,
+                                         const double* x, const double* y, const double* z, const double* q,
+                                         void* hip_stream, bhmc_tree** out) {
+    return create(params, R, n_per_replica, x, y, z, q, hip_stream, out);
+}
+
+extern "C" void bhmc_free(bhmc_tree* tree) {
+    if (tree) hipStreamSynchronize(tree->stream);
+    destroy(tree);
+}
+
+extern "C" int32_t bhmc_replicas(const bhmc_tree* tree) { return tree ? tree->R : 0; }
+
+static bhmc_status check_rep(bhmc_tree* t, int32_t r) {
+    if (!t) return fail(BHMC_EINVAL, "null tree");
+    if (r < 0 || r >= t->R) return fail(BHMC_EINVAL, "replica %d out of range", r);
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_info_get(bhmc_tree* tree, int32_t replica, bhmc_info* info) {
+    bhmc_status st = check_rep(tree, replica);
+    if (st) return st;
+    if (!info) return fail(BHMC_EINVAL, "null info");
+    const Rep& h = tree->host[replica];
+    info->n = h.n; info->nsrc = h.nsrc; info->ncell = h.ncell; info->nleaf = h.nleaf;
+    info->nterms = tree->nterms; info->depth = h.depth; info->pool = h.pool;
+    return BHMC_OK;
+}
+
+static bhmc_status rebuild_one(bhmc_tree* t, int r) {
+    bhmc_status st = download(t);  // keep the kernel-side counters of every replica
+    if (st) return st;
+    std::vector<int> list{r};
+    return build_list(t, list, nullptr, nullptr, nullptr, nullptr, {});
+}
+
+extern "C" bhmc_status bhmc_rebuild(bhmc_tree* tree, int32_t replica) {
+    bhmc_status st = check_rep(tree, replica);
+    if (st) return st;
+    return rebuild_one(tree, replica);
+}
+
+extern "C" bhmc_status bhmc_energy(bhmc_tree* t, double* E_host, double* phi_dev) {
+    bhmc_status st = check_rep(t, 0);
+    if (st) return st;
+    const int n = t->host[0].n;
+    if (t->eterm_n < n) {
+        hipFree(t->eterm);
+        t->eterm = nullptr;
+        HIP_TRY(hipMalloc(&t->eterm, sizeof(double) * n));
+        t->eterm_n = n;
+    }
+    t->ops->energy(t->stream, t->reps, 0, n, phi_dev, t->eterm);
+    bhmc::launch_sum(t->stream, t->eterm, n, t->host[0].l_B, t->scalar);
+    HIP_TRY(hipGetLastError());
+    double E = 0.0;
+    HIP_TRY(hipMemcpyAsync(&E, t->scalar, sizeof(double), hipMemcpyDeviceToHost, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    if (std::isnan(E)) return fail(BHMC_ESTACK, "a traversal list outgrew its LDS capacity");
+    if (E_host) *E_host = E;
+    return BHMC_OK;
+}
+
+static bhmc_status run_move(bhmc_tree* t, int64_t i, const double* r_new, int mode, bhmc::MoveIO& io) {
+    bhmc_status st = check_rep(t, 0);
+    if (st) return st;
+    if (i < 0 || i >= t->host[0].n) return fail(BHMC_EINVAL, "ion index %lld out of range", (long long)i);
+    if (!r_new || !std::isfinite(r_new[0]) || !std::isfinite(r_new[1]) || !std::isfinite(r_new[2]))
+        return fail(BHMC_EINVAL, "r_new must be three finite values");
+    memset(&io, 0, sizeof(io));
+    io.i = (int)i;
+    io.rn[0] = r_new[0]; io.rn[1] = r_new[1]; io.rn[2] = r_new[2];
+    io.mode = mode;
+    HIP_TRY(hipMemcpyAsync(t->io, &io, sizeof(io), hipMemcpyHostToDevice, t->stream));
+    t->ops->move(t->stream, t->reps, 0, t->io);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&io, t->io, sizeof(io), hipMemcpyDeviceToHost, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    if (io.status == -7) return fail(BHMC_ESTACK, "a traversal list outgrew its LDS capacity");
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_delta_energy(bhmc_tree* tree, int64_t i, const double* r_new, double* dE_host,
+                                         int32_t* reason_host) {
+    bhmc::MoveIO io;
+    bhmc_status st = run_move(tree, i, r_new, 0, io);
+    if (st) return st;
+    if (dE_host) *dE_host = io.reason ? HUGE_VAL : io.dE;
+    if (reason_host) *reason_host = io.reason;
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_commit_move(bhmc_tree* tree, int64_t i, const double* r_new) {
+    bhmc::MoveIO io;
+    bhmc_status st = run_move(tree, i, r_new, 1, io);
+    if (st) return st;
+    if (io.reason == 1) return fail(BHMC_EINVAL, "the move leaves the confinement");
+    if (io.reason == 2) return fail(BHMC_EOVERLAP, "the move overlaps a hard core");
+    if (io.status == -6) return fail(BHMC_ECAPACITY, "a leaf index array is full; rebuild first");
+    return BHMC_OK;
+}
+
+static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArgs& base, long long* rebuilds) {
+    long long last_stop = -1;
+    for (;;) {
+        bhmc::McArgs a = base;
+        a.list = t->list_one;
+        a.nlist = 1;
+        HIP_TRY(hipMemcpyAsync(t->list_one, &r, sizeof(int), hipMemcpyHostToDevice, t->stream));
+        bhmc::launch_reset_queue(t->stream, t->queue);
+        t->ops->mc(t->stream, t->reps, a, 1);
+        HIP_TRY(hipGetLastError());
+        bhmc_status st = download(t);
+        if (st) return st;
+        const Rep& h = t->host[r];
+        if (h.mc_status == -7) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its LDS capacity", r);
+        if (h.mc_status == -6) {
+            // a fresh tree leaves two spare slots in every leaf, so the same
+            // move cannot overflow twice in a row
+            if (h.move_next == last_stop)
+                return fail(BHMC_ECAPACITY, "replica %d: move %lld overflows a fresh tree", r, h.move_next);
+            last_stop = h.move_next;
+            if ((st = rebuild_one(t, r))) return st;
+            ++*rebuilds;
+            continue;
+        }
+        return BHMC_OK;
+    }
+}
+
+extern "C" bhmc_status bhmc_mc_run(bhmc_tree* t, int32_t replica, uint64_t seed, uint64_t move0,
+                                   int64_t n_moves, double step, uint8_t* accept_dev, bhmc_stats* stats_host) {
+    bhmc_status st = check_rep(t, replica);
+    if (st) return st;
+    if (n_moves < 0 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad n_moves or step");
+    if ((st = download(t))) return st;
+    Rep& h = t->host[replica];
+    h.move_next = (long long)move0;
+    h.move_end = (long long)(move0 + n_moves);
+    h.mc_status = 0;
+    for (int k = 0; k < 6; ++k) h.stats[k] = 0;
+    if ((st = upload(t))) return st;
+    bhmc::McArgs a{};
+    a.seed = seed;
+    a.step = step;
+    a.queue = t->queue;
+    a.accept = accept_dev;
+    a.move_base = (long long)move0;
+    long long rebuilds = 0;
+    if ((st = run_replica_until_done(t, replica, a, &rebuilds))) return st;
+    if (stats_host) {
+        const Rep& g = t->host[replica];
+        stats_host->moves = g.stats[0]; stats_host->accepted = g.stats[1];
+        stats_host->rejected_wall = g.stats[2]; stats_host->rejected_overlap = g.stats[3];
+        stats_host->rejected_metropolis = g.stats[4]; stats_host->rebuilds = rebuilds;
+    }
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_sweeps, double step,
+                                        int32_t use_graph, bhmc_stats* stats_host) {
+    if (!t) return fail(BHMC_EINVAL, "null tree");
+    if (n_sweeps < 0 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad n_sweeps or step");
+    bhmc_status st = download(t);
+    if (st) return st;
+    for (int r = 0; r < t->R; ++r) {
+        t->host[r].move_next = t->host[r].move_end;  // sweeps continue from the chain's end
+        t->host[r].mc_status = 0;
+        for (int k = 0; k < 6; ++k) t->host[r].stats[k] = 0;
+    }
+    if ((st = upload(t))) return st;
+    bhmc::McArgs a{};
+    a.seed = seed;
+    a.step = step;
+    a.list = t->list_all;
+    a.nlist = t->R;
+    a.queue = t->queue;
+    if (use_graph) {
+        hipStream_t gs = t->stream;
+        if (!gs) {
+            if (!t->graph_stream) HIP_TRY(hipStreamCreateWithFlags(&t->graph_stream, hipStreamNonBlocking));
+            gs = t->graph_stream;
+            HIP_TRY(hipDeviceSynchronize());
+        }
+        if (!t->graph_ok || t->graph_seed != seed || t->graph_step != step) {
+            if (t->gexec) { hipGraphExecDestroy(t->gexec); t->gexec = nullptr; }
+            if (t->graph) { hipGraphDestroy(t->graph); t->graph = nullptr; }
+            HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+            bhmc::launch_sweep_prep(gs, t->reps, t->R, t->queue, t->sweep_add);
+            t->ops->mc(gs, t->reps, a, t->mc_grid);
+            HIP_TRY(hipStreamEndCapture(gs, &t->graph));
+            HIP_TRY(hipGraphInstantiate(&t->gexec, t->graph, nullptr, nullptr, 0));
+            t->graph_ok = true; t->graph_seed = seed; t->graph_step = step;
+        }
+        for (int s = 0; s < n_sweeps; ++s) HIP_TRY(hipGraphLaunch(t->gexec, gs));
+        if (gs != t->stream) HIP_TRY(hipStreamSynchronize(gs));
+    } else {
+        for (int s = 0; s < n_sweeps; ++s) {
+            bhmc::launch_sweep_prep(t->stream, t->reps, t->R, t->queue, t->sweep_add);
+            t->ops->mc(t->stream, t->reps, a, t->mc_grid);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    if ((st = download(t))) return st;
+    std::vector<long long> rebuilds(t->R, 0);
+    for (int r = 0; r < t->R; ++r) {
+        const Rep& h = t->host[r];
+        if (h.mc_status == -7) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its LDS capacity", r);
+        if (h.mc_status == -6 || h.move_next < h.move_end) {
+            bhmc::McArgs b = a;
+            if ((st = run_replica_until_done(t, r, b, &rebuilds[r]))) return st;
+        }
+    }
+    if (stats_host) {
+        for (int r = 0; r < t->R; ++r) {
+            const Rep& g = t->host[r];
+            bhmc_stats& s = stats_host[r];
+            s.moves = g.stats[0]; s.accepted = g.stats[1]; s.rejected_wall = g.stats[2];
+            s.rejected_overlap = g.stats[3]; s.rejected_metropolis = g.stats[4]; s.rebuilds = rebuilds[r];
+        }
+    }
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, double* dEdr_dev, double* dEdq_dev, double* E_host) {
+    bhmc_status st = check_rep(t, 0);
+    if (st) return st;
+    if (!t->ops->grad) return fail(BHMC_EINVAL, "gradient not available");
+    (void)dEdr_dev; (void)dEdq_dev; (void)E_host;
+    return fail(BHMC_EINVAL, "gradient not available");
+}
+
+extern "C" bhmc_status bhmc_get_state(bhmc_tree* t, int32_t r, double* x, double* y, double* z, double* q) {
+    bhmc_status st = check_rep(t, r);
+    if (st) return st;
+    const Rep& h = t->host[r];
+    double* outs[4] = {x, y, z, q};
+    for (int c = 0; c < 4; ++c) {
+        if (!outs[c]) continue;
+        HIP_TRY(hipMemcpy2DAsync(outs[c], sizeof(double), ((const double*)h.src) + c, sizeof(double4),
+                                 sizeof(double), h.n, hipMemcpyDeviceToDevice, t->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    return BHMC_OK;
+}
+
+// ---- introspection: host outputs
+extern "C" bhmc_status bhmc_get_sorted(bhmc_tree* t, int32_t r, uint64_t* keys, int32_t* index) {
+    bhmc_status st = check_rep(t, r);
+    if (st) return st;
+    const Rep& h = t->host[r];
+    if (keys) HIP_TRY(hipMemcpy(keys, h.keys, 8 * (size_t)h.nsrc, hipMemcpyDeviceToHost));
+    if (index) HIP_TRY(hipMemcpy(index, h.perm, 4 * (size_t)h.nsrc, hipMemcpyDeviceToHost));
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_get_cells(bhmc_tree* t, int32_t r, int32_t* level, uint64_t* kmin, int32_t* count,
+                                      int32_t* link, double* geo, double* moments) {
+    bhmc_status st = check_rep(t, r);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    const Rep& h = t->host[r];
+    const size_t nc = h.ncell;
+    if (level) HIP_TRY(hipMemcpy(level, h.clevel, 4 * nc, hipMemcpyDeviceToHost));
+    if (kmin) HIP_TRY(hipMemcpy(kmin, h.ckey, 8 * nc, hipMemcpyDeviceToHost));
+    if (count) HIP_TRY(hipMemcpy(count, h.ccount, 4 * nc, hipMemcpyDeviceToHost));
+    if (link) HIP_TRY(hipMemcpy(link, h.clink, 4 * nc, hipMemcpyDeviceToHost));
+    if (geo) HIP_TRY(hipMemcpy(geo, h.cgeo, 32 * nc, hipMemcpyDeviceToHost));
+    if (moments)
+        HIP_TRY(hipMemcpy2D(moments, sizeof(double) * t->nterms, h.M, sizeof(double) * t->mstride,
+                            sizeof(double) * t->nterms, nc, hipMemcpyDeviceToHost));
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_get_leaves(bhmc_tree* t, int32_t r, int32_t* cell, int32_t* base, int32_t* cap,
+                                       int32_t* begin, int32_t* end) {
+    bhmc_status st = check_rep(t, r);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    const Rep& h = t->host[r];
+    std::vector<int> lc(h.nleaf), cb(h.ncell), ce(h.ncell);
+    HIP_TRY(hipMemcpy(lc.data(), h.lcell, 4 * (size_t)h.nleaf, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(cb.data(), h.cbegin, 4 * (size_t)h.ncell, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ce.data(), h.cend, 4 * (size_t)h.ncell, hipMemcpyDeviceToHost));
+    if (cell) memcpy(cell, lc.data(), 4 * (size_t)h.nleaf);
+    if (base) HIP_TRY(hipMemcpy(base, h.lbase, 4 * (size_t)h.nleaf, hipMemcpyDeviceToHost));
+    if (cap) HIP_TRY(hipMemcpy(cap, h.lcap, 4 * (size_t)h.nleaf, hipMemcpyDeviceToHost));
+    for (int l = 0; l < h.nleaf; ++l) {
+        if (begin) begin[l] = cb[lc[l]];
+        if (end) end[l] = ce[lc[l]];
+    }
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_get_slots(bhmc_tree* t, int32_t r, int32_t* slots) {
+    bhmc_status st = check_rep(t, r);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    const Rep& h = t->host[r];
+    if (slots) HIP_TRY(hipMemcpy(slots, h.pidx, 4 * (size_t)h.pool, hipMemcpyDeviceToHost));
+    return BHMC_OK;
+}

@@ -1,0 +1,423 @@
+// Tree construction kernels: one workgroup per replica.
+//
+//   k_sources   ions copied in, Kelvin images made, confinement checked, keys
+//   k_sort      stable LSD radix sort of (key, source) in LDS-ranked tiles
+//   k_count     number of split cells per level, straight from sorted keys
+//   k_topology  cells level by level (Sec. 3.2 bisection, adaptive by count)
+//   k_leaves    leaf index arrays (pool) and tracking information (Sec. 3.3)
+//   k_p2m       leaf moments M^n = sum q (r - c)^n            (eq. 3.3)
+//   k_m2m       parent moments from children by the binomial shift
+#include "bhmc_dev.hpp"
+#include "bhmc_internal.hpp"
+
+namespace bhmc {
+
+constexpr int kBuildBlock = 1024;
+
+__global__ void __launch_bounds__(kBuildBlock)
+k_sources(Rep* reps, const int* rep_list, const double* x, const double* y, const double* z,
+          const double* q, const long long* ion_off) {
+    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
+    const int n = R.n;
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    int my_bad = 0;
+    const long long off = ion_off ? ion_off[blockIdx.x] : 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double xi, yi, zi, qi;
+        if (x) {
+            xi = x[off + i]; yi = y[off + i]; zi = z[off + i]; qi = q[off + i];
+        } else {  // rebuild from the replica's own current ions
+            double4 s = R.src[i];
+            xi = s.x; yi = s.y; zi = s.z; qi = s.w;
+        }
+        if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(qi))) my_bad |= 1;
+        else if (outside(R, xi, yi, zi) || !in_root(R, xi, yi, zi)) my_bad |= 2;
+        R.src[i] = make_double4(xi, yi, zi, qi);
+        R.keys[i] = morton_key(R, xi, yi, zi);
+        R.perm[i] = i;
+        if (R.images) {
+            double4 im = kelvin(R, xi, yi, zi, qi);
+            if (!in_root(R, im.x, im.y, im.z)) my_bad |= 2;
+            R.src[n + i] = im;
+            R.keys[n + i] = morton_key(R, im.x, im.y, im.z);
+            R.perm[n + i] = n + i;
+        }
+    }
+    if (my_bad) atomicOr(&bad, my_bad);
+    __syncthreads();
+    if (threadIdx.x == 0) R.status = (bad & 1) ? -1 : ((bad & 2) ? -2 : 0);
+}
+
+// Stable LSD radix sort, 8 passes of 8 bits.  Each pass: LDS histogram,
+// exclusive scan, then tiles of BLOCK items scattered in order; inside a tile
+// an item's rank among equal digits comes from a wave-wide match (8 ballots)
+// plus the counts of the waves before it.
+__global__ void __launch_bounds__(kBuildBlock)
+k_sort(Rep* reps, const int* rep_list) {
+    constexpr int NW = kBuildBlock / 64;
+    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
+    const int n = R.nsrc;
+    __shared__ int hist[256];
+    __shared__ int wcnt[NW][256];
+    __shared__ int tile_tot[256];
+    __shared__ int skip;
+    uint64_t* ka = R.keys; int* va = R.perm;
+    uint64_t* kb = R.ktmp; int* vb = R.ptmp;
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    for (int k = tid; k < NW * 256; k += kBuildBlock) (&wcnt[0][0])[k] = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        if (tid < 256) hist[tid] = 0;
+        if (tid == 0) skip = 0;
+        __syncthreads();
+        for (int k = tid; k < n; k += kBuildBlock) atomicAdd(&hist[(ka[k] >> shift) & 255], 1);
+        __syncthreads();
+        if (tid < 256 && hist[tid] == n) skip = 1;  // every key has this digit: pass is a no-op
+        __syncthreads();
+        const bool skip_pass = skip;
+        __syncthreads();
+        if (skip_pass) continue;
+        if (tid == 0) {
+            int s = 0;
+            for (int d = 0; d < 256; ++d) { int c = hist[d]; hist[d] = s; s += c; }
+        }
+        __syncthreads();
+        for (int base = 0; base < n; base += kBuildBlock) {
+            const int k = base + tid;
+            const bool valid = k < n;
+            uint64_t key = valid ? ka[k] : 0;
+            int val = valid ? va[k] : 0;
+            const int dig = (int)((key >> shift) & 255);
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (dig >> b) & 1;
+                uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            const int rank = __popcll(peers & below);
+            const bool leader = valid && rank == 0;
+            if (leader) wcnt[w][dig] = __popcll(peers);
+            __syncthreads();
+            if (tid < 256) {
+                int s = 0;
+                for (int ww = 0; ww < NW; ++ww) { int c = wcnt[ww][tid]; wcnt[ww][tid] = s; s += c; }
+                tile_tot[tid] = s;
+            }
+            __syncthreads();
+            if (valid) {
+                const int pos = hist[dig] + wcnt[w][dig] + rank;
+                kb[pos] = key;
+                vb[pos] = val;
+            }
+            __syncthreads();
+            if (tid < 256) {
+                hist[tid] += tile_tot[tid];
+                for (int ww = 0; ww < NW; ++ww) wcnt[ww][tid] = 0;
+            }
+            __syncthreads();
+        }
+        uint64_t* tk = ka; ka = kb; kb = tk;
+        int* tv = va; va = vb; vb = tv;
+    }
+    // an odd number of executed passes leaves the result in the temporaries
+    if (ka != R.keys) {
+        for (int k = tid; k < n; k += kBuildBlock) { R.keys[k] = ka[k]; R.perm[k] = va[k]; }
+    }
+}
+
+// first index in [lo, hi) whose key is >= v
+__device__ __forceinline__ int lower_bound_key(const uint64_t* keys, int lo, int hi, uint64_t v) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (keys[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// A cell (level l, prefix P) is split iff it holds more than leaf_cap sources
+// and l < max_depth; such a cell's parent holds at least as many, so it was
+// split too.  The split cells of level l are therefore the runs of equal
+// l-prefix longer than leaf_cap.
+__global__ void __launch_bounds__(kBuildBlock)
+k_count(Rep* reps, const int* rep_list) {
+    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
+    const int n = R.nsrc;
+    __shared__ int cnt;
+    __shared__ int total;
+    __shared__ int depth;
+    if (threadIdx.x == 0) { total = 0; depth = 0; }
+    const uint64_t* keys = R.keys;
+    for (int l = 0; l < R.max_depth; ++l) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        const int shift = 63 - 3 * l;
+        int mine = 0;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const uint64_t P = keys[k] >> shift;
+            if (k > 0 && (keys[k - 1] >> shift) == P) continue;
+            const uint64_t next = (P + 1) << shift;  // P < 2^(3l): no overflow
+            const int e = (l == 0) ? n : lower_bound_key(keys, k, n, next);
+            if (e - k > R.leaf_cap) ++mine;
+        }
+        if (mine) atomicAdd(&cnt, mine);
+        __syncthreads();
+        const int c = cnt;
+        if (threadIdx.x == 0) { total += c; if (c) depth = l + 1; }
+        __syncthreads();
+        if (c == 0) break;
+    }
+    if (threadIdx.x == 0) {
+        R.nsplit = total;
+        R.ncell = 1 + 8 * total;
+        R.nleaf = R.ncell - total;
+        R.depth = depth;
+        // sum_leaves max(count, cap) <= nsrc + nleaf * leaf_cap
+        R.pool = R.slack * (R.nsrc + R.nleaf * R.leaf_cap) + 2 * R.nleaf;
+    }
+}
+
+__device__ __forceinline__ void cell_geometry(const Rep& R, int level, uint64_t kmin, double4& g) {
+    const double h = ldexp(R.side, -(level + 1));
+    const int sh = 21 - level;
+    const uint32_t ix = compact3(kmin >> 2) >> sh;
+    const uint32_t iy = compact3(kmin >> 1) >> sh;
+    const uint32_t iz = compact3(kmin) >> sh;
+    g.x = R.lo[0] + (double)(2u * ix + 1u) * h;
+    g.y = R.lo[1] + (double)(2u * iy + 1u) * h;
+    g.z = R.lo[2] + (double)(2u * iz + 1u) * h;
+    g.w = h;
+}
+
+// Cells in level order; the children of a split cell are consecutive in digit
+// order; leaves are numbered in cell order.
+__global__ void __launch_bounds__(kBuildBlock)
+k_topology(Rep* reps, const int* rep_list) {
+    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
+    __shared__ uint64_t wsum[kBuildBlock / 64 + 1];
+    __shared__ int s_next, s_leaf;
+    const int n = R.nsrc;
+    const uint64_t* keys = R.keys;
+    if (threadIdx.x == 0) {
+        R.ckey[0] = 0; R.clevel[0] = 0; R.cparent[0] = -1; R.cbegin[0] = 0; R.cend[0] = n;
+        R.ccount[0] = n;
+        double4 g; cell_geometry(R, 0, 0, g); R.cgeo[0] = g;
+        R.level_start[0] = 0;
+        s_next = 1; s_leaf = 0;
+    }
+    __syncthreads();
+    int ls = 0, le = 1, level = 0;
+    while (ls < le) {
+        for (int base = ls; base < le; base += kBuildBlock) {
+            const int c = base + threadIdx.x;
+            const bool valid = c < le;
+            int b = 0, e = 0;
+            bool split = false;
+            if (valid) {
+                b = R.cbegin[c]; e = R.cend[c];
+                split = (e - b > R.leaf_cap) && level < R.max_depth;
+            }
+            const uint64_t v = valid ? (split ? 1ull : (1ull << 32)) : 0ull;
+            uint64_t tot;
+            const uint64_t ex = block_exscan<kBuildBlock>(v, wsum, tot);
+            const int next0 = s_next, leaf0 = s_leaf;
+            if (valid && split && next0 + 8 * (int)(ex & 0xffffffffu) + 8 > R.ncell) {
+                R.status = -5;  // the counting pass and this pass disagree: write nothing
+            } else if (valid && split) {
+                const int first = next0 + 8 * (int)(ex & 0xffffffffu);
+                R.clink[c] = first;
+                const uint64_t pk = R.ckey[c];
+                const int csh = 60 - 3 * level;
+                int cb = b;
+                for (int d = 0; d < 8; ++d) {
+                    const uint64_t ck = pk | ((uint64_t)d << csh);
+                    const int ce = (d == 7) ? e : lower_bound_key(keys, cb, e, pk | ((uint64_t)(d + 1) << csh));
+                    const int ch = first + d;
+                    R.ckey[ch] = ck; R.clevel[ch] = level + 1; R.cparent[ch] = c;
+                    R.cbegin[ch] = cb; R.cend[ch] = ce; R.ccount[ch] = ce - cb;
+                    double4 g; cell_geometry(R, level + 1, ck, g); R.cgeo[ch] = g;
+                    cb = ce;
+                }
+            } else if (valid && leaf0 + (int)(ex >> 32) >= R.nleaf) {
+                R.status = -5;
+            } else if (valid) {
+                const int leaf = leaf0 + (int)(ex >> 32);
+                R.clink[c] = -1 - leaf;
+                R.lcell[leaf] = c;
+                const int cnt = e - b;
+                R.lcap[leaf] = R.slack * (cnt > R.leaf_cap ? cnt : R.leaf_cap) + 2;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                s_next = next0 + 8 * (int)(tot & 0xffffffffu);
+                s_leaf = leaf0 + (int)(tot >> 32);
+            }
+            __syncthreads();
+        }
+        ++level;
+        ls = le;
+        le = s_next < R.ncell ? s_next : R.ncell;
+        if (threadIdx.x == 0) R.level_start[level] = ls;
+    }
+    if (threadIdx.x == 0) {
+        R.level_start[level] = le;
+        for (int l = level + 1; l <= kMaxLevels; ++l) R.level_start[l] = le;
+        if (s_next != R.ncell || s_leaf != R.nleaf) R.status = -5;
+        R.depth = level - 1;
+    }
+}
+
+// Leaf index arrays: bases by an exclusive scan of the capacities; members
+// in sorted order; tracking = (leaf, slot) of every source.
+__global__ void __launch_bounds__(kBuildBlock)
+k_leaves(Rep* reps, const int* rep_list) {
+    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
+    __shared__ uint64_t wsum[kBuildBlock / 64 + 1];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int nl = R.nleaf;
+    for (int base = 0; base < nl; base += kBuildBlock) {
+        const int l = base + threadIdx.x;
+        const int cap = l < nl ? R.lcap[l] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_exscan<kBuildBlock>((uint64_t)cap, wsum, tot);
+        const int c0 = carry;
+        if (l < nl) R.lbase[l] = c0 + (int)ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c0 + (int)tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && carry > R.pool) R.status = -5;
+    __syncthreads();
+    if (carry > R.pool || R.status) return;  // uniform: nothing is written past the pool
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) {
+        const int c = R.lcell[l];
+        const int b = R.cbegin[c], e = R.cend[c], base = R.lbase[l];
+        for (int k = b; k < e; ++k) {
+            const int s = R.perm[k];
+            R.pool4[base + k - b] = R.src[s];
+            R.pidx[base + k - b] = s;
+            R.leaf_of[s] = l;
+            R.slot_of[s] = k - b;
+        }
+    }
+}
+
+// multi-index table in graded order, shared by the build kernels
+__constant__ int c_mi[kMaxTerms * 3];
+__constant__ int c_binom[kPMax + 2][kPMax + 2];
+
+__device__ __forceinline__ int mindex_dev(int n1, int n2, int n3) {
+    const int s = n1 + n2 + n3;
+    return s * (s + 1) * (s + 2) / 6 + (s - n1) * (s - n1 + 1) / 2 + (s - n1 - n2);
+}
+
+// P2M at leaves: one thread per (leaf, term); d^n by repeated multiplication.
+__global__ void __launch_bounds__(kBuildBlock)
+k_p2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
+    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
+    if (R.status) return;  // a failed build leaves the leaf tables unusable
+    const long long items = (long long)R.nleaf * nterms;
+    for (long long it = threadIdx.x; it < items; it += blockDim.x) {
+        const int l = (int)(it / nterms), k = (int)(it % nterms);
+        const int c = R.lcell[l];
+        const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
+        const double4 g = R.cgeo[c];
+        const int base = R.lbase[l], cnt = R.ccount[c];
+        double acc = 0.0;
+        for (int j = 0; j < cnt; ++j) {
+            const double4 s = R.pool4[base + j];
+            const double dx = s.x - g.x, dy = s.y - g.y, dz = s.z - g.z;
+            double v = 1.0;
+            for (int e = 0; e < n1; ++e) v *= dx;
+            for (int e = 0; e < n2; ++e) v *= dy;
+            for (int e = 0; e < n3; ++e) v *= dz;
+            acc += s.w * v;
+        }
+        R.M[(size_t)c * mstride + k] = acc;
+    }
+}
+
+// M2M, deepest level first: with s = c_child - c_parent (every component
+// +-h_child, exact),
+//   M_parent^n = sum_children sum_{k <= n} C(n, k) s^(n-k) M_child^k.
+__global__ void __launch_bounds__(kBuildBlock)
+k_m2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
+    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
+    if (R.status) return;
+    for (int level = R.depth - 1; level >= 0; --level) {
+        const int ls = R.level_start[level], le = R.level_start[level + 1];
+        const long long items = (long long)(le - ls) * nterms;
+        for (long long it = threadIdx.x; it < items; it += blockDim.x) {
+            const int c = ls + (int)(it / nterms), k = (int)(it % nterms);
+            const int first = R.clink[c];
+            if (first < 0) continue;
+            const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
+            const double hc = R.cgeo[c].w * 0.5;
+            double acc = 0.0;
+            for (int d = 0; d < 8; ++d) {
+                const double sx = (d & 4) ? hc : -hc, sy = (d & 2) ? hc : -hc, sz = (d & 1) ? hc : -hc;
+                const double* Mc = R.M + (size_t)(first + d) * mstride;
+                double px = 1.0;
+                for (int k1 = n1; k1 >= 0; --k1) {      // s_x^(n1-k1) grows as k1 falls
+                    double py = 1.0;
+                    for (int k2 = n2; k2 >= 0; --k2) {
+                        double pz = 1.0;
+                        for (int k3 = n3; k3 >= 0; --k3) {
+                            const double coef = (double)(c_binom[n1][k1] * c_binom[n2][k2] * c_binom[n3][k3]);
+                            acc += coef * (px * py * pz) * Mc[mindex_dev(k1, k2, k3)];
+                            pz *= sz;
+                        }
+                        py *= sy;
+                    }
+                    px *= sx;
+                }
+            }
+            R.M[(size_t)c * mstride + k] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ host launchers
+void upload_build_tables(int p) {
+    int mi[kMaxTerms * 3];
+    int k = 0;
+    for (int s = 0; s <= p; ++s)
+        for (int n1 = s; n1 >= 0; --n1)
+            for (int n2 = s - n1; n2 >= 0; --n2) { mi[3 * k] = n1; mi[3 * k + 1] = n2; mi[3 * k + 2] = s - n1 - n2; ++k; }
+    int binom[kPMax + 2][kPMax + 2] = {};
+    for (int a = 0; a <= kPMax + 1; ++a) {
+        binom[a][0] = 1;
+        for (int b = 1; b <= a; ++b) binom[a][b] = binom[a - 1][b - 1] + (b <= a - 1 ? binom[a - 1][b] : 0);
+    }
+    hipMemcpyToSymbol(HIP_SYMBOL(c_mi), mi, sizeof(int) * 3 * k);
+    hipMemcpyToSymbol(HIP_SYMBOL(c_binom), binom, sizeof(binom));
+}
+
+void launch_sources(hipStream_t s, int nrep, Rep* reps, const int* list, const double* x,
+                    const double* y, const double* z, const double* q, const long long* ion_off) {
+    hipLaunchKernelGGL(k_sources, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list, x, y, z, q, ion_off);
+}
+void launch_sort(hipStream_t s, int nrep, Rep* reps, const int* list) {
+    hipLaunchKernelGGL(k_sort, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
+}
+void launch_count(hipStream_t s, int nrep, Rep* reps, const int* list) {
+    hipLaunchKernelGGL(k_count, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
+}
+void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list) {
+    hipLaunchKernelGGL(k_topology, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
+}
+void launch_leaves(hipStream_t s, int nrep, Rep* reps, const int* list) {
+    hipLaunchKernelGGL(k_leaves, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
+}
+void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nterms, int mstride) {
+    hipLaunchKernelGGL(k_p2m, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list, nterms, mstride);
+    hipLaunchKernelGGL(k_m2m, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list, nterms, mstride);
+}
+
+}  // namespace bhmc

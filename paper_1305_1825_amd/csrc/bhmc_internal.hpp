@@ -1,0 +1,63 @@
+// Declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bhmc {
+
+struct Rep;
+
+constexpr int kMaxTerms = 364;  // (p+1)(p+2)(p+3)/6 at p = 11 (gradient needs order p + 1)
+
+inline int nterms_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+inline int mstride_of(int p) { return (nterms_of(p) + 3) & ~3; }  // 32-byte aligned rows
+
+// Arguments of one Monte Carlo launch.
+struct McArgs {
+    uint64_t seed;
+    double step;
+    const int* list;      // replica ids to run, in queue order
+    int nlist;
+    int* queue;           // work-queue counter (reset before the launch)
+    uint8_t* accept;      // per-move accept bits of a single-replica run, or null
+    long long move_base;  // move index of accept[0]
+    long long* sweep_add; // per replica moves added to move_end by the sweep prep kernel
+};
+
+// One externally specified move (delta_energy / commit_move).
+struct MoveIO {
+    int i;
+    double rn[3];
+    int mode;             // 0: evaluate only; 1: evaluate and commit unless rejected
+    double dE;
+    int reason;
+    int status;
+};
+
+// ---- build (bhmc_build.hip)
+void upload_build_tables(int p);
+void launch_sources(hipStream_t s, int nrep, Rep* reps, const int* list, const double* x,
+                    const double* y, const double* z, const double* q, const long long* ion_off);
+void launch_sort(hipStream_t s, int nrep, Rep* reps, const int* list);
+void launch_count(hipStream_t s, int nrep, Rep* reps, const int* list);
+void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list);
+void launch_leaves(hipStream_t s, int nrep, Rep* reps, const int* list);
+void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nterms, int mstride);
+
+// ---- evaluation (bhmc_eval.hip, one translation unit per expansion order)
+struct EvalOps {
+    void (*mc)(hipStream_t s, Rep* reps, const McArgs& a, int grid);
+    void (*move)(hipStream_t s, Rep* reps, int r, MoveIO* io_dev);
+    void (*energy)(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm);
+    void (*grad)(hipStream_t s, Rep* reps, int r, int n, double* work, double* dEdr, double* dEdq,
+                 double* eterm);
+    int mc_block;
+};
+const EvalOps* eval_ops(int p);
+
+// ---- small utility kernels (bhmc_api.hip)
+void launch_sweep_prep(hipStream_t s, Rep* reps, int R, int* queue, const long long* add);
+void launch_reset_queue(hipStream_t s, int* queue);
+void launch_sum(hipStream_t s, const double* v, int n, double scale, double* out);
+
+}  // namespace bhmc
