@@ -1,0 +1,208 @@
+"""Benchmark: Metropolis trial moves per second of the treecode path on one MI355X.
+
+A step is one pass of the whole path over one synthetic system: build the
+octree with images, keys, sort, moments (from the same initial positions every
+step), then run the system's trial moves with the treecode energy change,
+Metropolis test and local commit, all on the device.
+
+Headline workload: spherical colloid, N = 10,000 monovalent ions plus one
+Kelvin image each, theta = 0.5, p = 6, leaf 16, 100,000 trial moves per step.
+Extra objects: the batched-replica workload (256 replicas of uneven N, one
+persistent launch per sweep under a hipGraph) and the roofline of the dominant
+kernel, plus the CPU oracle timed on the host on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def csrc_hash() -> str:
+    h = hashlib.sha1()
+    d = os.path.join(ROOT, "paper_1305_1825_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def algorithmic_bytes_per_move(c, n_sample=400):
+    """Bytes a move must touch at least, from the oracle's interaction counts:
+    40 B per visited cell (centre, half side, count, link), 8 B per moment of
+    every far cell, 32 B per near source (x, y, z, q), and for an accepted move
+    a read and a write of every moment on the four root paths."""
+    import oracle as O
+    P = c["params"]
+    o = O.Tree(P, c["x"], c["y"], c["z"], c["q"])
+    inf = o.info()
+    nterms = inf["nterms"]
+    n = len(c["x"])
+    tot_v = tot_f = tot_s = 0
+    evald = 0
+    for m in range(n_sample):
+        i, d, _ = O.draw_move(c["seed"], 0, m, n, c["step"])
+        rn = np.array([c["x"][i], c["y"][i], c["z"][i]]) + d
+        _, reason, cnt = o.delta(i, rn, counts=True)
+        if reason == 0:
+            tot_v += cnt[0]; tot_f += cnt[1]; tot_s += cnt[2]
+            evald += 1
+    per_eval = (40.0 * tot_v + 8.0 * nterms * tot_f + 32.0 * tot_s) / max(evald, 1)
+    frac_eval = evald / n_sample
+    depth = inf["depth"] + 1
+    paths = 4 if P["images"] else 2
+    commit = paths * depth * nterms * 16.0
+    return dict(per_move=per_eval * frac_eval + commit * 0.9 * frac_eval,
+                per_eval=per_eval, visited=tot_v / max(evald, 1), far=tot_f / max(evald, 1),
+                near=tot_s / max(evald, 1), eval_fraction=frac_eval, commit_bytes=commit)
+
+
+def run_plain(c, steps, warmup):
+    import torch
+    from paper_1305_1825_amd import bhmc
+    P = c["params"]
+    x, y, z, q = (torch.as_tensor(a, dtype=torch.float64, device="cuda:0") for a in (c["x"], c["y"], c["z"], c["q"]))
+    moves = c["moves"]
+    stream = torch.cuda.current_stream()
+    mc_ms = []
+    last = None
+
+    def one_step(timed):
+        nonlocal last
+        t = bhmc.Tree(P, x, y, z, q)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        st = t.mc_run(seed=c["seed"], n_moves=moves, step=c["step"])
+        ev1.record(stream)
+        ev1.synchronize()
+        if timed:
+            mc_ms.append(ev0.elapsed_time(ev1))
+        last = st
+        t.close()
+
+    for _ in range(warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(wall=wall, mc_ms=mc_ms, stats=last)
+
+
+def run_batched(R, sweeps, seed=0):
+    import torch
+    from paper_1305_1825_amd import bhmc, workloads as W
+    sizes = [int(v) for v in W.replica_sizes(R, seed=seed)]
+    reps = [W.batched_replica(r, n, seed=seed) for r, n in enumerate(sizes)]
+    Ps = [rp[0] for rp in reps]
+    cat = [torch.as_tensor(np.concatenate([rp[k] for rp in reps]), dtype=torch.float64, device="cuda:0")
+           for k in range(1, 5)]
+    t = bhmc.Tree(Ps, *cat, n_per_replica=sizes)
+    t.batch_sweep(seed=seed, n_sweeps=1, step=1.0, use_graph=True)  # warm-up sweep, builds the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = t.batch_sweep(seed=seed, n_sweeps=sweeps, step=1.0, use_graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    moves = sum(s["moves"] for s in st)
+    t.close()
+    return dict(moves=moves, wall=wall, moves_per_s=moves / wall, replicas=R, sweeps=sweeps,
+                n_min=min(sizes), n_max=max(sizes), n_total=sum(sizes))
+
+
+def cpu_baseline(c, seconds=12.0):
+    import oracle as O
+    P = c["params"]
+    o = O.Tree(P, c["x"], c["y"], c["z"], c["q"])
+    chunk = 500
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and done < c["moves"]:
+        o.mc_run(seed=c["seed"], replica=0, move0=done, n_moves=chunk, step=c["step"])
+        done += chunk
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="moves/s", cores=1, kind="oracle",
+                sample="first %d trial moves of the N=10000 colloid chain (serial C treecode, "
+                       "build excluded), %.1f s" % (done, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--moves", type=int, default=100000)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-sweeps", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(replicas would shard one per GPU with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1305_1825_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    c = W.config_colloid_10k()
+    c["moves"] = args.moves
+    print("bench: plain chain %s, %d moves/step, %d steps" % (c["name"], c["moves"], args.steps),
+          file=sys.stderr, flush=True)
+    res = run_plain(c, args.steps, args.warmup)
+    total_moves = args.steps * c["moves"]
+    value = total_moves / res["wall"]
+    ms_per_step = 1000.0 * res["wall"] / args.steps
+    mc_ms = float(np.mean(res["mc_ms"]))
+    ab = algorithmic_bytes_per_move(c)
+    achieved = ab["per_move"] * c["moves"] / (mc_ms / 1000.0) / 1e9
+    out = {
+        "metric": "Metropolis trial moves/sec (treecode dE, 1 GPU)",
+        "value": value,
+        "unit": "moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "colloid a=10 Q=-50 eps 2/80, N=10000 ions + 10000 Kelvin images, "
+                               "shell 10.5<r<40, hard core 0.5, theta=0.5, p=6, leaf 16, "
+                               "%d trial moves per step (build included)" % c["moves"],
+                   "chain": "plain single chain", "seed": c["seed"]},
+        "stats": res["stats"],
+        "mc_kernel_ms_per_step": mc_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_mc (p=6)", "algorithmic_bytes_per_move": ab["per_move"],
+                     "per_move_counts": {k: ab[k] for k in ("visited", "far", "near", "eval_fraction")}},
+        "csrc": csrc_hash(),
+    }
+    if not args.no_batched:
+        print("bench: batched replicas", file=sys.stderr, flush=True)
+        b = run_batched(256, args.batched_sweeps)
+        b["ratio_vs_plain"] = b["moves_per_s"] / value
+        out["batched"] = b
+    if not args.no_cpu:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(c)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -45,7 +45,8 @@ typedef enum {
     BHMC_ENOMEM = -4,     /* device allocation failed                         */
     BHMC_EHIP = -5,       /* a HIP runtime call failed                        */
     BHMC_ECAPACITY = -6,  /* a leaf's index array is full (see bhmc_commit_move) */
-    BHMC_ESTACK = -7      /* a traversal list outgrew its on-chip capacity    */
+    BHMC_ESTACK = -7,     /* a traversal list outgrew its on-chip capacity    */
+    BHMC_EINTERNAL = -8   /* a device-side index check failed; the handle must be freed */
 } bhmc_status;
 
 /* Rejection reasons reported with an infinite energy change. */

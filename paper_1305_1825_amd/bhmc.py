@@ -13,11 +13,11 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbhmc.so")
+LIB_PATH = os.environ.get("BHMC_LIB") or os.path.join(_HERE, "libbhmc.so")
 
 BHMC_OK = 0
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EOUTSIDE", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP",
-                -6: "ECAPACITY", -7: "ESTACK"}
+                -6: "ECAPACITY", -7: "ESTACK", -8: "EINTERNAL"}
 REASON_NONE, REASON_WALL, REASON_OVERLAP = 0, 1, 2
 
 

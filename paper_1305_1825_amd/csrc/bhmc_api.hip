@@ -40,6 +40,16 @@ __global__ void k_sweep_prep(Rep* reps, int R, int* queue, const long long* add)
 
 __global__ void k_reset_queue(int* queue) { *queue = 0; }
 
+__global__ void k_unpack(const double4* src, int n, double* x, double* y, double* z, double* q) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double4 v = src[i];
+        if (x) x[i] = v.x;
+        if (y) y[i] = v.y;
+        if (z) z[i] = v.z;
+        if (q) q[i] = v.w;
+    }
+}
+
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
     s = a + b;
     const double bb = s - a;
@@ -88,7 +98,9 @@ struct bhmc_tree {
     int R = 0, p = 0, nterms = 0, mstride = 0;
     hipStream_t stream = nullptr;
     std::vector<bhmc_params> params;
-    std::vector<Rep> host;           // mirror of the descriptor table
+    Rep* host = nullptr;             // pinned mirror of the descriptor table
+    char* pin = nullptr;             // pinned staging for every other host<->device copy
+    size_t pin_bytes = 0;
     Rep* reps = nullptr;             // device descriptor table
     std::vector<void*> arena1, arena2;
     const bhmc::EvalOps* ops = nullptr;
@@ -168,6 +180,37 @@ static void fill_rep(Rep& r, const bhmc_params& P, int64_t n) {
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Every host<->device copy goes through pinned memory the library allocated
+// itself (hipHostMalloc); caller or stack memory is never handed to HIP.
+static bhmc_status ensure_pin(bhmc_tree* t, size_t bytes) {
+    if (bytes <= t->pin_bytes) return BHMC_OK;
+    size_t want = std::max(bytes, (size_t)1 << 16);
+    if (t->pin) { hipHostFree(t->pin); t->pin = nullptr; t->pin_bytes = 0; }
+    HIP_TRY(hipHostMalloc((void**)&t->pin, want, hipHostMallocDefault));
+    t->pin_bytes = want;
+    return BHMC_OK;
+}
+
+static bhmc_status d2h(bhmc_tree* t, void* dst, const void* src_dev, size_t bytes) {
+    if (!bytes) return BHMC_OK;
+    bhmc_status st = ensure_pin(t, bytes);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(t->pin, src_dev, bytes, hipMemcpyDeviceToHost, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    memcpy(dst, t->pin, bytes);
+    return BHMC_OK;
+}
+
+static bhmc_status h2d(bhmc_tree* t, void* dst_dev, const void* src, size_t bytes) {
+    if (!bytes) return BHMC_OK;
+    bhmc_status st = ensure_pin(t, bytes);
+    if (st) return st;
+    memcpy(t->pin, src, bytes);
+    HIP_TRY(hipMemcpyAsync(dst_dev, t->pin, bytes, hipMemcpyHostToDevice, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));  // the staging buffer is reused at once
+    return BHMC_OK;
+}
+
 struct Carver {
     char* base; size_t off = 0;
     template <class T> T* take(size_t count) {
@@ -215,11 +258,12 @@ static bhmc_status alloc_phase2(bhmc_tree* t, int r) {
 }
 
 static bhmc_status upload(bhmc_tree* t) {
-    HIP_TRY(hipMemcpyAsync(t->reps, t->host.data(), sizeof(Rep) * t->R, hipMemcpyHostToDevice, t->stream));
+    HIP_TRY(hipMemcpyAsync(t->reps, t->host, sizeof(Rep) * t->R, hipMemcpyHostToDevice, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));  // the host mirror may change right after
     return BHMC_OK;
 }
 static bhmc_status download(bhmc_tree* t) {
-    HIP_TRY(hipMemcpyAsync(t->host.data(), t->reps, sizeof(Rep) * t->R, hipMemcpyDeviceToHost, t->stream));
+    HIP_TRY(hipMemcpyAsync(t->host, t->reps, sizeof(Rep) * t->R, hipMemcpyDeviceToHost, t->stream));
     HIP_TRY(hipStreamSynchronize(t->stream));
     return BHMC_OK;
 }
@@ -229,6 +273,7 @@ static const char* status_name(int s) {
         case -1: return "a non-finite coordinate or charge";
         case -2: return "an ion outside the confinement, or a source outside the root cube";
         case -5: return "inconsistent tree sizes";
+        case -8: return "a device-side index check failed while filling the leaf arrays";
         default: return "error";
     }
 }
@@ -244,11 +289,12 @@ static bhmc_status build_list(bhmc_tree* t, const std::vector<int>& list, const 
     HIP_TRY(hipMalloc(&dlist, sizeof(int) * nr));
     HIP_TRY(hipMalloc(&doff, sizeof(long long) * nr));
     struct Guard { int* a; long long* b; ~Guard() { hipFree(a); hipFree(b); } } guard{dlist, doff};
-    HIP_TRY(hipMemcpyAsync(dlist, list.data(), sizeof(int) * nr, hipMemcpyHostToDevice, t->stream));
-    if (x) HIP_TRY(hipMemcpyAsync(doff, ion_off.data(), sizeof(long long) * nr, hipMemcpyHostToDevice, t->stream));
+    bhmc_status st = h2d(t, dlist, list.data(), sizeof(int) * nr);
+    if (st) return st;
+    if (x && (st = h2d(t, doff, ion_off.data(), sizeof(long long) * nr))) return st;
     for (int r : list)
-        if (!t->host[r].src) { bhmc_status st = alloc_phase1(t, r); if (st) return st; }
-    bhmc_status st = upload(t);
+        if (!t->host[r].src && (st = alloc_phase1(t, r))) return st;
+    st = upload(t);
     if (st) return st;
     bhmc::launch_sources(t->stream, nr, t->reps, dlist, x, y, z, q, x ? doff : nullptr);
     bhmc::launch_sort(t->stream, nr, t->reps, dlist);
@@ -281,6 +327,8 @@ static void destroy(bhmc_tree* t) {
     for (void* p : t->arena2) if (p) hipFree(p);
     hipFree(t->reps); hipFree(t->queue); hipFree(t->list_all); hipFree(t->list_one);
     hipFree(t->sweep_add); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar);
+    if (t->host) hipHostFree(t->host);
+    if (t->pin) hipHostFree(t->pin);
     delete t;
 }
 
@@ -303,7 +351,10 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     t->mstride = bhmc::mstride_of(t->p);
     t->stream = (hipStream_t)stream;
     t->params.assign(params, params + R);
-    t->host.resize(R);
+    if (hipHostMalloc((void**)&t->host, sizeof(Rep) * R, hipHostMallocDefault) != hipSuccess) {
+        delete t;
+        return fail(BHMC_ENOMEM, "pinned descriptor mirror");
+    }
     t->arena1.assign(R, nullptr);
     t->arena2.assign(R, nullptr);
     t->ops = bhmc::eval_ops(t->p);
@@ -318,7 +369,8 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     if (hipMalloc(&t->sweep_add, sizeof(long long) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "sweep"));
     if (hipMalloc(&t->io, sizeof(bhmc::MoveIO)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "io"));
     if (hipMalloc(&t->scalar, sizeof(double) * 4) != hipSuccess) return bail(fail(BHMC_ENOMEM, "scalar"));
-    bhmc::upload_build_tables(t->p);
+    if (ensure_pin(t, 1 << 16) != BHMC_OK) return bail(BHMC_ENOMEM);
+    if (bhmc::upload_build_tables(t->p, t->pin) != hipSuccess) return bail(fail(BHMC_EHIP, "constant tables"));
     std::vector<int> list(R);
     std::iota(list.begin(), list.end(), 0);
     bhmc_status st = build_list(t, list, x, y, z, q, off);
@@ -328,9 +380,9 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_per[a] > n_per[b]; });
     std::vector<long long> add(n_per, n_per + R);
-    if (hipMemcpy(t->list_all, order.data(), sizeof(int) * R, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t->sweep_add, add.data(), sizeof(long long) * R, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(fail(BHMC_EHIP, "upload of the sweep tables failed"));
+    if ((st = h2d(t, t->list_all, order.data(), sizeof(int) * R)) ||
+        (st = h2d(t, t->sweep_add, add.data(), sizeof(long long) * R)))
+        return bail(st);
     int dev = 0, ncu = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -400,9 +452,13 @@ extern "C" bhmc_status bhmc_energy(bhmc_tree* t, double* E_host, double* phi_dev
     bhmc::launch_sum(t->stream, t->eterm, n, t->host[0].l_B, t->scalar);
     HIP_TRY(hipGetLastError());
     double E = 0.0;
-    HIP_TRY(hipMemcpyAsync(&E, t->scalar, sizeof(double), hipMemcpyDeviceToHost, t->stream));
-    HIP_TRY(hipStreamSynchronize(t->stream));
-    if (std::isnan(E)) return fail(BHMC_ESTACK, "a traversal list outgrew its LDS capacity");
+    if ((st = d2h(t, &E, t->scalar, sizeof(double)))) return st;
+    if (std::isnan(E)) {
+        if ((st = download(t))) return st;
+        const int d = t->host[0].err_detail;
+        if (d > 1) return fail(BHMC_EINTERNAL, "device index check %d failed in the energy traversal", d);
+        return fail(BHMC_ESTACK, "a traversal list outgrew its LDS capacity");
+    }
     if (E_host) *E_host = E;
     return BHMC_OK;
 }
@@ -417,12 +473,16 @@ static bhmc_status run_move(bhmc_tree* t, int64_t i, const double* r_new, int mo
     io.i = (int)i;
     io.rn[0] = r_new[0]; io.rn[1] = r_new[1]; io.rn[2] = r_new[2];
     io.mode = mode;
-    HIP_TRY(hipMemcpyAsync(t->io, &io, sizeof(io), hipMemcpyHostToDevice, t->stream));
+    if ((st = h2d(t, t->io, &io, sizeof(io)))) return st;
     t->ops->move(t->stream, t->reps, 0, t->io);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(&io, t->io, sizeof(io), hipMemcpyDeviceToHost, t->stream));
-    HIP_TRY(hipStreamSynchronize(t->stream));
+    if ((st = d2h(t, &io, t->io, sizeof(io)))) return st;
     if (io.status == -7) return fail(BHMC_ESTACK, "a traversal list outgrew its LDS capacity");
+    if (io.status == -8) {
+        bhmc_status s2 = download(t);
+        if (s2) return s2;
+        return fail(BHMC_EINTERNAL, "device index check %d failed", t->host[0].err_detail);
+    }
     return BHMC_OK;
 }
 
@@ -452,7 +512,8 @@ static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArg
         bhmc::McArgs a = base;
         a.list = t->list_one;
         a.nlist = 1;
-        HIP_TRY(hipMemcpyAsync(t->list_one, &r, sizeof(int), hipMemcpyHostToDevice, t->stream));
+        bhmc_status st0 = h2d(t, t->list_one, &r, sizeof(int));
+        if (st0) return st0;
         bhmc::launch_reset_queue(t->stream, t->queue);
         t->ops->mc(t->stream, t->reps, a, 1);
         HIP_TRY(hipGetLastError());
@@ -460,6 +521,8 @@ static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArg
         if (st) return st;
         const Rep& h = t->host[r];
         if (h.mc_status == -7) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its LDS capacity", r);
+        if (h.mc_status == -8)
+            return fail(BHMC_EINTERNAL, "replica %d: device index check %d failed at move %lld", r, h.err_detail, h.move_next);
         if (h.mc_status == -6) {
             // a fresh tree leaves two spare slots in every leaf, so the same
             // move cannot overflow twice in a row
@@ -552,6 +615,8 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
     for (int r = 0; r < t->R; ++r) {
         const Rep& h = t->host[r];
         if (h.mc_status == -7) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its LDS capacity", r);
+        if (h.mc_status == -8)
+            return fail(BHMC_EINTERNAL, "replica %d: device index check %d failed at move %lld", r, h.err_detail, h.move_next);
         if (h.mc_status == -6 || h.move_next < h.move_end) {
             bhmc::McArgs b = a;
             if ((st = run_replica_until_done(t, r, b, &rebuilds[r]))) return st;
@@ -580,23 +645,20 @@ extern "C" bhmc_status bhmc_get_state(bhmc_tree* t, int32_t r, double* x, double
     bhmc_status st = check_rep(t, r);
     if (st) return st;
     const Rep& h = t->host[r];
-    double* outs[4] = {x, y, z, q};
-    for (int c = 0; c < 4; ++c) {
-        if (!outs[c]) continue;
-        HIP_TRY(hipMemcpy2DAsync(outs[c], sizeof(double), ((const double*)h.src) + c, sizeof(double4),
-                                 sizeof(double), h.n, hipMemcpyDeviceToDevice, t->stream));
-    }
+    hipLaunchKernelGGL(bhmc::k_unpack, dim3(std::max(1, std::min(1024, (h.n + 255) / 256))), dim3(256), 0,
+                       t->stream, (const double4*)h.src, h.n, x, y, z, q);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(t->stream));
     return BHMC_OK;
 }
 
-// ---- introspection: host outputs
+// ---- introspection: host outputs, staged through pinned memory
 extern "C" bhmc_status bhmc_get_sorted(bhmc_tree* t, int32_t r, uint64_t* keys, int32_t* index) {
     bhmc_status st = check_rep(t, r);
     if (st) return st;
     const Rep& h = t->host[r];
-    if (keys) HIP_TRY(hipMemcpy(keys, h.keys, 8 * (size_t)h.nsrc, hipMemcpyDeviceToHost));
-    if (index) HIP_TRY(hipMemcpy(index, h.perm, 4 * (size_t)h.nsrc, hipMemcpyDeviceToHost));
+    if (keys && (st = d2h(t, keys, h.keys, 8 * (size_t)h.nsrc))) return st;
+    if (index && (st = d2h(t, index, h.perm, 4 * (size_t)h.nsrc))) return st;
     return BHMC_OK;
 }
 
@@ -604,17 +666,19 @@ extern "C" bhmc_status bhmc_get_cells(bhmc_tree* t, int32_t r, int32_t* level, u
                                       int32_t* link, double* geo, double* moments) {
     bhmc_status st = check_rep(t, r);
     if (st) return st;
-    HIP_TRY(hipStreamSynchronize(t->stream));
     const Rep& h = t->host[r];
     const size_t nc = h.ncell;
-    if (level) HIP_TRY(hipMemcpy(level, h.clevel, 4 * nc, hipMemcpyDeviceToHost));
-    if (kmin) HIP_TRY(hipMemcpy(kmin, h.ckey, 8 * nc, hipMemcpyDeviceToHost));
-    if (count) HIP_TRY(hipMemcpy(count, h.ccount, 4 * nc, hipMemcpyDeviceToHost));
-    if (link) HIP_TRY(hipMemcpy(link, h.clink, 4 * nc, hipMemcpyDeviceToHost));
-    if (geo) HIP_TRY(hipMemcpy(geo, h.cgeo, 32 * nc, hipMemcpyDeviceToHost));
-    if (moments)
-        HIP_TRY(hipMemcpy2D(moments, sizeof(double) * t->nterms, h.M, sizeof(double) * t->mstride,
-                            sizeof(double) * t->nterms, nc, hipMemcpyDeviceToHost));
+    if (level && (st = d2h(t, level, h.clevel, 4 * nc))) return st;
+    if (kmin && (st = d2h(t, kmin, h.ckey, 8 * nc))) return st;
+    if (count && (st = d2h(t, count, h.ccount, 4 * nc))) return st;
+    if (link && (st = d2h(t, link, h.clink, 4 * nc))) return st;
+    if (geo && (st = d2h(t, geo, h.cgeo, 32 * nc))) return st;
+    if (moments) {
+        std::vector<double> rows(nc * (size_t)t->mstride);
+        if ((st = d2h(t, rows.data(), h.M, sizeof(double) * rows.size()))) return st;
+        for (size_t c = 0; c < nc; ++c)
+            memcpy(moments + c * t->nterms, rows.data() + c * t->mstride, sizeof(double) * t->nterms);
+    }
     return BHMC_OK;
 }
 
@@ -622,15 +686,14 @@ extern "C" bhmc_status bhmc_get_leaves(bhmc_tree* t, int32_t r, int32_t* cell, i
                                        int32_t* begin, int32_t* end) {
     bhmc_status st = check_rep(t, r);
     if (st) return st;
-    HIP_TRY(hipStreamSynchronize(t->stream));
     const Rep& h = t->host[r];
     std::vector<int> lc(h.nleaf), cb(h.ncell), ce(h.ncell);
-    HIP_TRY(hipMemcpy(lc.data(), h.lcell, 4 * (size_t)h.nleaf, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(cb.data(), h.cbegin, 4 * (size_t)h.ncell, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(ce.data(), h.cend, 4 * (size_t)h.ncell, hipMemcpyDeviceToHost));
+    if ((st = d2h(t, lc.data(), h.lcell, 4 * (size_t)h.nleaf))) return st;
+    if ((st = d2h(t, cb.data(), h.cbegin, 4 * (size_t)h.ncell))) return st;
+    if ((st = d2h(t, ce.data(), h.cend, 4 * (size_t)h.ncell))) return st;
     if (cell) memcpy(cell, lc.data(), 4 * (size_t)h.nleaf);
-    if (base) HIP_TRY(hipMemcpy(base, h.lbase, 4 * (size_t)h.nleaf, hipMemcpyDeviceToHost));
-    if (cap) HIP_TRY(hipMemcpy(cap, h.lcap, 4 * (size_t)h.nleaf, hipMemcpyDeviceToHost));
+    if (base && (st = d2h(t, base, h.lbase, 4 * (size_t)h.nleaf))) return st;
+    if (cap && (st = d2h(t, cap, h.lcap, 4 * (size_t)h.nleaf))) return st;
     for (int l = 0; l < h.nleaf; ++l) {
         if (begin) begin[l] = cb[lc[l]];
         if (end) end[l] = ce[lc[l]];
@@ -641,8 +704,7 @@ extern "C" bhmc_status bhmc_get_leaves(bhmc_tree* t, int32_t r, int32_t* cell, i
 extern "C" bhmc_status bhmc_get_slots(bhmc_tree* t, int32_t r, int32_t* slots) {
     bhmc_status st = check_rep(t, r);
     if (st) return st;
-    HIP_TRY(hipStreamSynchronize(t->stream));
     const Rep& h = t->host[r];
-    if (slots) HIP_TRY(hipMemcpy(slots, h.pidx, 4 * (size_t)h.pool, hipMemcpyDeviceToHost));
+    if (slots && (st = d2h(t, slots, h.pidx, 4 * (size_t)h.pool))) return st;
     return BHMC_OK;
 }

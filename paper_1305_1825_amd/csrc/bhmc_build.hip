@@ -296,9 +296,12 @@ k_leaves(Rep* reps, const int* rep_list) {
     if (carry > R.pool || R.status) return;  // uniform: nothing is written past the pool
     for (int l = threadIdx.x; l < nl; l += blockDim.x) {
         const int c = R.lcell[l];
+        if (c < 0 || c >= R.ncell) { R.status = -8; continue; }
         const int b = R.cbegin[c], e = R.cend[c], base = R.lbase[l];
+        if (b < 0 || e > R.nsrc || b > e || base + (e - b) > R.pool) { R.status = -8; continue; }
         for (int k = b; k < e; ++k) {
             const int s = R.perm[k];
+            if (s < 0 || s >= R.nsrc) { R.status = -8; continue; }
             R.pool4[base + k - b] = R.src[s];
             R.pidx[base + k - b] = s;
             R.leaf_of[s] = l;
@@ -325,9 +328,11 @@ k_p2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
     for (long long it = threadIdx.x; it < items; it += blockDim.x) {
         const int l = (int)(it / nterms), k = (int)(it % nterms);
         const int c = R.lcell[l];
+        if (c < 0 || c >= R.ncell) continue;
         const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
         const double4 g = R.cgeo[c];
         const int base = R.lbase[l], cnt = R.ccount[c];
+        if (cnt < 0 || base < 0 || base + cnt > R.pool) continue;
         double acc = 0.0;
         for (int j = 0; j < cnt; ++j) {
             const double4 s = R.pool4[base + j];
@@ -355,7 +360,7 @@ k_m2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
         for (long long it = threadIdx.x; it < items; it += blockDim.x) {
             const int c = ls + (int)(it / nterms), k = (int)(it % nterms);
             const int first = R.clink[c];
-            if (first < 0) continue;
+            if (first < 0 || first + 8 > R.ncell) continue;
             const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
             const double hc = R.cgeo[c].w * 0.5;
             double acc = 0.0;
@@ -384,19 +389,19 @@ k_m2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
 }
 
 // ------------------------------------------------------------ host launchers
-void upload_build_tables(int p) {
-    int mi[kMaxTerms * 3];
+hipError_t upload_build_tables(int p, void* pinned) {
+    int* mi = (int*)pinned;                        // 3 * kMaxTerms ints
+    int (*binom)[kPMax + 2] = (int (*)[kPMax + 2])(mi + 3 * kMaxTerms);
     int k = 0;
     for (int s = 0; s <= p; ++s)
         for (int n1 = s; n1 >= 0; --n1)
             for (int n2 = s - n1; n2 >= 0; --n2) { mi[3 * k] = n1; mi[3 * k + 1] = n2; mi[3 * k + 2] = s - n1 - n2; ++k; }
-    int binom[kPMax + 2][kPMax + 2] = {};
-    for (int a = 0; a <= kPMax + 1; ++a) {
-        binom[a][0] = 1;
-        for (int b = 1; b <= a; ++b) binom[a][b] = binom[a - 1][b - 1] + (b <= a - 1 ? binom[a - 1][b] : 0);
-    }
-    hipMemcpyToSymbol(HIP_SYMBOL(c_mi), mi, sizeof(int) * 3 * k);
-    hipMemcpyToSymbol(HIP_SYMBOL(c_binom), binom, sizeof(binom));
+    for (int a = 0; a <= kPMax + 1; ++a)
+        for (int b = 0; b <= kPMax + 1; ++b)
+            binom[a][b] = (b == 0) ? 1 : (b > a ? 0 : binom[a - 1][b - 1] + (b <= a - 1 ? binom[a - 1][b] : 0));
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_mi), mi, sizeof(int) * 3 * k);
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_binom), binom, sizeof(int) * (kPMax + 2) * (kPMax + 2));
+    return e;
 }
 
 void launch_sources(hipStream_t s, int nrep, Rep* reps, const int* list, const double* x,

@@ -14,6 +14,15 @@ constexpr int kMaxDepth = 21;
 constexpr int kMaxLevels = kMaxDepth + 1;
 constexpr int kPMax = 10;
 
+// Device-side index checks: a failed check records one of these codes and the
+// access is skipped, so a corrupted index can never reach memory.
+enum ErrDetail {
+    kErrNone = 0, kErrStack = 1, kErrFrontCell = 2, kErrChildLink = 3, kErrFarCell = 4,
+    kErrNearLeaf = 5, kErrNearSlots = 6, kErrOvlLeaf = 7, kErrPathCell = 8, kErrPathDepth = 9,
+    kErrCommitLeaf = 10, kErrCommitSlot = 11, kErrCommitSource = 12, kErrFlagCell = 13,
+    kErrMomentCell = 14, kErrBuildPerm = 15, kErrBuildCell = 16, kErrBuildPool = 17
+};
+
 // Per-replica descriptor.  Host writes parameters and pointers, kernels write
 // sizes, statuses and the Monte Carlo counters.
 struct Rep {
@@ -46,8 +55,8 @@ struct Rep {
     int* pidx;                     // source index of each slot
     // ---- Monte Carlo state
     long long move_next, move_end; // next move index, one past the last
-    int mc_status;                 // 0, or BHMC_ECAPACITY / BHMC_ESTACK
-    int _pad;
+    int mc_status;                 // 0, or BHMC_ECAPACITY / BHMC_ESTACK / BHMC_EINTERNAL
+    int err_detail;                // which device-side index check failed (0 = none)
     long long stats[6];            // moves, accepted, wall, overlap, metropolis, unused
 };
 

@@ -166,6 +166,7 @@ __device__ void flush_far(const Rep& R, Trav<NTG, BLOCK>& S, int far_n, double (
     for (int j = threadIdx.x; j < far_n; j += BLOCK) {
         const uint32_t e = S.farl[j];
         const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
+        if (c >= R.ncell) { S.err = kErrFarCell; continue; }
         const double4 g = R.cgeo[c];
         const double* Mc = (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32);
         add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], Mc));
@@ -179,9 +180,24 @@ __device__ void flush_near(const Rep& R, Trav<NTG, BLOCK>& S, int near_n, double
     for (int j = threadIdx.x; j < near_n; j += BLOCK) {
         const uint32_t e = S.nearl[j];
         const int c = (int)(e & kCellMask);
-        const int leaf = -1 - R.clink[c];
-        S.near_base[j] = R.lbase[leaf];
-        S.near_pre[j] = R.ccount[c];
+        int base = 0, cnt = 0;
+        if (c < R.ncell) {
+            const int leaf = -1 - R.clink[c];
+            if (leaf >= 0 && leaf < R.nleaf) {
+                base = R.lbase[leaf];
+                cnt = R.ccount[c];
+                if (cnt < 0 || cnt > R.lcap[leaf] || base < 0 || base + cnt > R.pool) {
+                    S.err = kErrNearSlots;
+                    cnt = 0;
+                }
+            } else {
+                S.err = kErrNearLeaf;
+            }
+        } else {
+            S.err = kErrNearLeaf;
+        }
+        S.near_base[j] = base;
+        S.near_pre[j] = cnt;
     }
     __syncthreads();
     int carry = 0;
@@ -237,16 +253,22 @@ __device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK>& S) {
     const double x = S.tx[t], y = S.ty[t], z = S.tz[t];
     const double reach = sqrt(R.tau2) + 1e-12 * R.side;
     const double reach2 = reach * reach;
-    int cur = 0, fs = S.n_ovl;
+    // n_ovl counts every insert attempt; entries past OVLCAP were never stored
+    int cur = 0, fs = S.n_ovl < Trav<NTG, BLOCK>::OVLCAP ? S.n_ovl : Trav<NTG, BLOCK>::OVLCAP;
     for (int j = threadIdx.x; j < fs; j += BLOCK) S.front[0][j] = S.ovl[j];
     while (fs > 0) {
         if (threadIdx.x == 0) s_cnt[cur ^ 1] = 0;
         __syncthreads();
         for (int j = threadIdx.x; j < fs; j += BLOCK) {
             const int c = (int)S.front[cur][j];
+            if (c < 0 || c >= R.ncell) { S.err = kErrOvlLeaf; continue; }
             const int link = R.clink[c];
+            if (link >= 0 && link + 8 > R.ncell) { S.err = kErrChildLink; continue; }
             if (link < 0) {
-                const int leaf = -1 - link, base = R.lbase[leaf], cnt = R.ccount[c];
+                const int leaf = -1 - link;
+                if (leaf >= R.nleaf) { S.err = kErrOvlLeaf; continue; }
+                const int base = R.lbase[leaf], cnt = R.ccount[c];
+                if (cnt < 0 || base < 0 || base + cnt > R.pool) { S.err = kErrOvlLeaf; continue; }
                 for (int k = 0; k < cnt; ++k) {
                     const int sid = R.pidx[base + k];
                     if (sid >= R.n || sid == S.ovl_ex) continue;
@@ -261,7 +283,7 @@ __device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK>& S) {
                     if (box_dist2(R.cgeo[ch], x, y, z) <= reach2) {
                         const int slot = atomicAdd(&s_cnt[cur ^ 1], 1);
                         if (slot < Trav<NTG, BLOCK>::FCAP) S.front[cur ^ 1][slot] = (uint32_t)ch;
-                        else S.err = 1;
+                        else S.err = kErrStack;
                     }
                 }
             }
@@ -301,10 +323,14 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
             const int fi = (e & kFlagIon) ? 1 : 0, fk = (e & kFlagImg) ? 1 : 0;
             int kind = 0, link = 0;
             uint32_t cdir = e & kFlagDirect;
-            if (valid) {
+            if (valid && c >= R.ncell) {
+                S.err = kErrFrontCell;
+            } else if (valid) {
                 const int np = R.ccount[c] - fi - fk;
                 link = R.clink[c];
-                if (np > 0) {
+                if (link >= 0 && link + 8 > R.ncell) {
+                    S.err = kErrChildLink;
+                } else if (np > 0) {
                     if (cdir) {
                         kind = link >= 0 ? 3 : 2;
                     } else {
@@ -318,7 +344,7 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
                                 const double reach = sqrt(R.tau2) + 1e-12 * R.side;
                                 if (box_dist2(g, S.tx[t], S.ty[t], S.tz[t]) <= reach * reach) {
                                     const int slot = atomicAdd(&S.n_ovl, 1);
-                                    if (slot < TS::OVLCAP) S.ovl[slot] = (uint32_t)c; else S.err = 1;
+                                    if (slot < TS::OVLCAP) S.ovl[slot] = (uint32_t)c; else S.err = kErrStack;
                                 }
                             }
                         } else if (np > R.n0 && link >= 0) {
@@ -365,7 +391,7 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
         fs = next_n;
     }
     if (failed) {
-        if (tid == 0) S.err = 1;
+        if (tid == 0) S.err = kErrStack;
         __syncthreads();
         return level;
     }
@@ -375,6 +401,7 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
             const int f = it / NTERM, k = it % NTERM;
             const uint32_t e = S.flagl[f];
             const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
+            if (c >= R.ncell) { S.err = kErrFlagCell; S.Mx[f][k] = 0.0; continue; }
             const double4 g = R.cgeo[c];
             double m = R.M[(size_t)c * MSTR + k];
             if (e & kFlagIon) { const double4 s = S.es_i[t]; m = m - s.w * mono(k, s.x - g.x, s.y - g.y, s.z - g.z); }
@@ -385,13 +412,14 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
         for (int f = tid; f < nflag; f += BLOCK) {
             const uint32_t e = S.flagl[f];
             const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
+            if (c >= R.ncell) continue;
             const double4 g = R.cgeo[c];
             add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], S.Mx[f]));
         }
     }
     flush_far<NTG, BLOCK>(R, S, far_n, acc);
     flush_near<NTG, BLOCK>(R, S, near_n, acc);  // ends with a barrier
-    if (S.ovl_t >= 0 && S.n_ovl > 0) overlap_below_far<NTG, BLOCK>(R, S);
+    if (S.ovl_t >= 0 && S.n_ovl > 0 && S.err == 0) overlap_below_far<NTG, BLOCK>(R, S);
     const int lane = lane_id(), w = wave_id();
 #pragma unroll
     for (int k = 0; k < NTG; ++k) {
@@ -415,9 +443,10 @@ struct McShared {
     uint64_t key[4];
     double4 contrib[4];       // (position, charge) of the four contributions
     int ok;
+    int err;                  // index-check failure seen while descending or committing
 };
 
-struct MoveOut { double dE; int reason; int accepted; int stop; };
+struct MoveOut { double dE; int reason; int accepted; int stop; int detail; };
 
 constexpr double kInf = __builtin_huge_val();
 
@@ -444,7 +473,8 @@ __device__ void commit(const Rep& R, McShared& MS, int i) {
                 const int moved = R.pidx[bo + last];
                 R.pool4[bo + k] = R.pool4[bo + last];
                 R.pidx[bo + k] = moved;
-                R.slot_of[moved] = k;
+                if (moved >= 0 && moved < R.nsrc) R.slot_of[moved] = k;
+                else MS.err = kErrCommitSource;
                 R.ccount[co] = last;
                 const int cnt = R.ccount[cn], bn = R.lbase[ln];
                 R.pool4[bn + cnt] = nv;
@@ -466,6 +496,7 @@ __device__ void commit(const Rep& R, McShared& MS, int i) {
         const int l = rest % maxlen, j = rest / maxlen;
         if (l >= MS.plen[j]) continue;
         const int c = MS.path[j][l];
+        if (c < 0 || c >= R.ncell) continue;  // descents only store checked cells
         bool owner = true;
         for (int jj = 0; jj < j; ++jj)
             if (l < MS.plen[jj] && MS.path[jj][l] == c) owner = false;
@@ -491,7 +522,7 @@ template <int BLOCK>
 __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double rx,
                             double ry, double rz, double alpha, int mode) {
     const int tid = threadIdx.x;
-    MoveOut out{kInf, 0, 0, 0};
+    MoveOut out{kInf, 0, 0, 0, 0};
     const double4 si = R.src[i];
     if (outside(R, rx, ry, rz)) { out.reason = 1; return out; }
     const bool imgs = R.images != 0;
@@ -521,29 +552,37 @@ __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i
         MS.contrib[0] = si; MS.contrib[1] = sn; MS.contrib[2] = mo; MS.contrib[3] = mn;
     }
     if (tid < 4) { MS.path[tid][0] = 0; MS.plen[tid] = 0; }
+    if (tid == 0) MS.err = 0;
     __syncthreads();
-    // the four root paths descend one level per traversal level
-    auto hook = [&](int level) {
-        if (tid < nps && MS.plen[tid] == 0) {
-            const int c = MS.path[tid][level];
-            const int link = R.clink[c];
-            if (link >= 0) MS.path[tid][level + 1] = link + key_digit(MS.key[tid], level + 1);
-            else MS.plen[tid] = level + 1;
+    // one step of a root path: descend by the key's digit, or stop at the leaf
+    auto step = [&](int level) {
+        const int c = MS.path[tid][level];
+        const int link = (c >= 0 && c < R.ncell) ? R.clink[c] : -1;
+        if (c < 0 || c >= R.ncell || (link >= 0 && link + 8 > R.ncell)) {
+            MS.err = kErrPathCell;
+            MS.plen[tid] = level + 1;
+            MS.path[tid][level] = 0;
+        } else if (link >= 0 && level + 1 < kMaxLevels) {
+            MS.path[tid][level + 1] = link + key_digit(MS.key[tid], level + 1);
+        } else {
+            if (link >= 0) MS.err = kErrPathDepth;
+            MS.plen[tid] = level + 1;
         }
     };
+    // the four root paths descend one level per traversal level
+    auto hook = [&](int level) {
+        if (tid < nps && MS.plen[tid] == 0 && level < kMaxLevels) step(level);
+    };
     const int levels = traverse<2, BLOCK>(R, S, 2, hook);
-    if (S.err) { out.stop = -7; __syncthreads(); return out; }
+    if (S.err) { out.stop = S.err == kErrStack ? -7 : -8; out.detail = S.err; __syncthreads(); return out; }
     // the traversal may stop above a path's leaf (a cell holding only the
     // excluded sources, or the image's path): finish those descents
     if (tid < nps) {
-        for (int level = levels; MS.plen[tid] == 0; ++level) {
-            const int c = MS.path[tid][level];
-            const int link = R.clink[c];
-            if (link >= 0) MS.path[tid][level + 1] = link + key_digit(MS.key[tid], level + 1);
-            else MS.plen[tid] = level + 1;
-        }
+        for (int level = levels; MS.plen[tid] == 0 && level < kMaxLevels; ++level) step(level);
+        if (MS.plen[tid] == 0) { MS.err = kErrPathDepth; MS.plen[tid] = 1; MS.path[tid][0] = 0; }
     }
     __syncthreads();
+    if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
     const double po = S.res[0], pn = S.res[1];
     if (S.overlap || S.coincide) { out.reason = 2; __syncthreads(); return out; }
     const double q = si.w, l = R.l_B;
@@ -560,22 +599,43 @@ __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i
     else if (mode == 2) acc = true;
     if (!acc) { __syncthreads(); return out; }
     if (tid == 0) {
-        const int co = MS.path[0][MS.plen[0] - 1], cn = MS.path[1][MS.plen[1] - 1];
-        const int lio = -1 - R.clink[co], lin = -1 - R.clink[cn];
-        bool ok = true;
-        if (lin != lio && R.ccount[cn] + 1 > R.lcap[lin]) ok = false;
-        if (imgs) {
-            const int cmo = MS.path[2][MS.plen[2] - 1], cmn = MS.path[3][MS.plen[3] - 1];
-            const int lmo = -1 - R.clink[cmo], lmn = -1 - R.clink[cmn];
-            if (lmn != lmo) {
-                int c = R.ccount[cmn];
-                if (lin != lio) { if (lmn == lin) c += 1; if (lmn == lio) c -= 1; }
-                if (c + 1 > R.lcap[lmn]) ok = false;
+        // leaves of the four paths and every slot the commit will touch, checked
+        bool sane = true;
+        int leafc[4] = {0, 0, 0, 0}, leaf[4] = {0, 0, 0, 0};
+        for (int j = 0; j < nps; ++j) {
+            leafc[j] = MS.path[j][MS.plen[j] - 1];
+            const int link = R.clink[leafc[j]];
+            leaf[j] = -1 - link;
+            if (link >= 0 || leaf[j] >= R.nleaf) sane = false;
+        }
+        for (int part = 0; sane && part < nps / 2; ++part) {
+            const int s = part == 0 ? i : R.n + i;
+            if (s < 0 || s >= R.nsrc) { sane = false; break; }
+            const int lo = leaf[2 * part];
+            const int k = R.slot_of[s], cnt = R.ccount[leafc[2 * part]];
+            if (R.leaf_of[s] != lo || k < 0 || k >= cnt || cnt > R.lcap[lo] ||
+                R.lbase[lo] + cnt > R.pool || R.pidx[R.lbase[lo] + k] != s)
+                sane = false;
+        }
+        bool ok = sane;
+        if (sane) {
+            const int lio = leaf[0], lin = leaf[1];
+            if (lin != lio && R.ccount[leafc[1]] + 1 > R.lcap[lin]) ok = false;
+            if (imgs) {
+                const int lmo = leaf[2], lmn = leaf[3];
+                if (lmn != lmo) {
+                    int c = R.ccount[leafc[3]];
+                    if (lin != lio) { if (lmn == lin) c += 1; if (lmn == lio) c -= 1; }
+                    if (c + 1 > R.lcap[lmn]) ok = false;
+                }
             }
+        } else {
+            MS.err = kErrCommitSlot;
         }
         MS.ok = ok;
     }
     __syncthreads();
+    if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
     if (!MS.ok) { out.stop = -6; __syncthreads(); return out; }
     commit<BLOCK>(R, MS, i);
     out.accepted = 1;
@@ -620,13 +680,13 @@ __global__ void __launch_bounds__(kMcBlock) k_mc(Rep* reps, McArgs A) {
         long long m = Rs.move_next;
         const long long mend = Rs.move_end;
         long long st_moves = 0, st_acc = 0, st_wall = 0, st_ovl = 0, st_met = 0;
-        int status = 0;
+        int status = 0, detail = 0;
         for (; m < mend; ++m) {
             const Draw d = draw_move(A.seed, (uint32_t)r, (uint64_t)m, Rs.n, A.step);
             const double4 si = Rs.src[d.i];
             const MoveOut o = one_move<kMcBlock>(Rs, S, MS, d.i, si.x + d.dx, si.y + d.dy,
                                                  si.z + d.dz, d.alpha, 1);
-            if (o.stop) { status = o.stop; break; }
+            if (o.stop) { status = o.stop; detail = o.detail; break; }
             ++st_moves;
             if (o.accepted) ++st_acc;
             else if (o.reason == 1) ++st_wall;
@@ -639,6 +699,7 @@ __global__ void __launch_bounds__(kMcBlock) k_mc(Rep* reps, McArgs A) {
             Rep* g = reps + r;
             g->move_next = m;
             g->mc_status = status;
+            if (detail) g->err_detail = detail;
             g->stats[0] += st_moves; g->stats[1] += st_acc; g->stats[2] += st_wall;
             g->stats[3] += st_ovl; g->stats[4] += st_met;
         }
@@ -659,6 +720,7 @@ __global__ void __launch_bounds__(kMcBlock) k_move(Rep* reps, int r, MoveIO* io)
         io->dE = o.dE;
         io->reason = o.reason;
         io->status = o.stop;
+        if (o.detail) reps[r].err_detail = o.detail;
     }
 }
 
@@ -695,6 +757,7 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
         const int ion = t0 + tid;
         const double4 si = Rs.src[ion];
         const double ph = S.err ? __builtin_nan("") : S.res[tid];
+        if (S.err && tid == 0) reps[r].err_detail = S.err;
         double e = 0.5 * si.w * ph;
         if (Rs.geom == 1) {
             const double r2 = si.x * si.x + si.y * si.y + si.z * si.z;

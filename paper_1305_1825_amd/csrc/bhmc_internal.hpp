@@ -35,7 +35,7 @@ struct MoveIO {
 };
 
 // ---- build (bhmc_build.hip)
-void upload_build_tables(int p);
+hipError_t upload_build_tables(int p, void* pinned);  // pinned: >= 16 KiB of hipHostMalloc memory
 void launch_sources(hipStream_t s, int nrep, Rep* reps, const int* list, const double* x,
                     const double* y, const double* z, const double* q, const long long* ion_off);
 void launch_sort(hipStream_t s, int nrep, Rep* reps, const int* list);
