@@ -144,13 +144,13 @@ int32_t bhmc_replicas(const bhmc_tree* tree);
 
 bhmc_status bhmc_info_get(bhmc_tree* tree, int32_t replica, bhmc_info* info);
 
-/* Treecode total energy of replica 0 (host result):
+/* Treecode total energy of replica `replica` (host result):
  *   E = l_B [ 1/2 sum_i q_i phi_i(r_i) + 1/2 sum_i gamma a q_i^2 / (|r_i|^2 - a^2)
  *             + Q_center sum_i q_i / |r_i| ],
  * phi_i = potential at r_i from every source except ion i and its image,
  * evaluated by the MAC traversal of Sec. 3.2 with the expansion of eq. 3.3.
  * phi_dev (nullable): dev, n values, receives phi_i. */
-bhmc_status bhmc_energy(bhmc_tree* tree, double* E_host, double* phi_dev);
+bhmc_status bhmc_energy(bhmc_tree* tree, int32_t replica, double* E_host, double* phi_dev);
 
 /* Energy change of moving ion i of replica 0 to r_new (host, 3 values), on
  * the committed tree (Sec. 1: the particle's energy evaluated twice):
@@ -198,11 +198,21 @@ bhmc_status bhmc_mc_run(bhmc_tree* tree, int32_t replica, uint64_t seed, uint64_
 bhmc_status bhmc_batch_sweep(bhmc_tree* tree, uint64_t seed, int32_t n_sweeps, double step,
                              int32_t use_graph, bhmc_stats* stats_host);
 
-/* Gradient of the treecode energy E of bhmc_energy for replica 0, exact for
- * the interaction lists its traversal makes: dEdr_dev (dev, 3n values, x y z
- * per ion), dEdq_dev (dev, n values); moments are recomputed, not stored.
- * E_host (nullable) receives E. */
-bhmc_status bhmc_energy_grad(bhmc_tree* tree, double* dEdr_dev, double* dEdq_dev, double* E_host);
+/* Gradient of the treecode energy E of bhmc_energy for replica `replica`,
+ * exact for the interaction lists its traversal makes (each far pair term
+ * q_t q_j sum_n T_n(r_A - r_t) (r_j - r_A)^n of eq. 3.3 and each near pair
+ * q_t q_j / |r_t - r_j| is differentiated in both its points and charges; the
+ * images are mapped back to their ions by the chain rule through
+ * q_K = gamma a q / |r|, r_K = a^2 r / |r|^2).  It uses the replica's current
+ * moments, which equal a fresh evaluation from the current positions up to
+ * rounding (bhmc_rebuild refreshes them); nothing of the traversal is stored.
+ * Outputs: dEdr_dev (dev, 3n values, x y z per ion), dEdq_dev (dev, n
+ * values); E_host (nullable) receives E, bit-identical to bhmc_energy.  The
+ * far-field source side is summed with device atomics, so the gradient can
+ * differ between calls by rounding.  The library keeps a workspace of
+ * 8 (ncell * round4(C(p+3,3)) + 4 nsrc + 4 n) bytes per handle. */
+bhmc_status bhmc_energy_grad(bhmc_tree* tree, int32_t replica, double* dEdr_dev, double* dEdq_dev,
+                             double* E_host);
 
 /* Current ion positions and charges of a replica (dev outputs, n each). */
 bhmc_status bhmc_get_state(bhmc_tree* tree, int32_t replica, double* x, double* y, double* z,

@@ -65,12 +65,12 @@ SIGNATURES = {
     "bhmc_free": [_v],
     "bhmc_replicas": [_v],
     "bhmc_info_get": [_v, C.c_int32, C.POINTER(Info)],
-    "bhmc_energy": [_v, _d, _v],
+    "bhmc_energy": [_v, C.c_int32, _d, _v],
     "bhmc_delta_energy": [_v, C.c_int64, _d, _d, _i32],
     "bhmc_commit_move": [_v, C.c_int64, _d],
     "bhmc_mc_run": [_v, C.c_int32, C.c_uint64, C.c_uint64, C.c_int64, C.c_double, _v, C.POINTER(Stats)],
     "bhmc_batch_sweep": [_v, C.c_uint64, C.c_int32, C.c_double, C.c_int32, C.POINTER(Stats)],
-    "bhmc_energy_grad": [_v, _v, _v, _d],
+    "bhmc_energy_grad": [_v, C.c_int32, _v, _v, _d],
     "bhmc_get_state": [_v, C.c_int32, _v, _v, _v, _v],
     "bhmc_rebuild": [_v, C.c_int32],
     "bhmc_get_sorted": [_v, C.c_int32, _u64, _i32],
@@ -187,11 +187,11 @@ class Tree:
         return {k: int(getattr(inf, k)) for k, _ in Info._fields_}
 
     # ---------------------------------------------------------------- evaluation
-    def energy(self, with_phi=False):
+    def energy(self, with_phi=False, replica=0):
         torch = _torch()
         E = C.c_double()
-        phi = torch.empty(self.n_per[0], dtype=torch.float64, device=self.device) if with_phi else None
-        _check(lib().bhmc_energy(self.h, C.byref(E), phi.data_ptr() if with_phi else None), "energy")
+        phi = torch.empty(self.n_per[replica], dtype=torch.float64, device=self.device) if with_phi else None
+        _check(lib().bhmc_energy(self.h, replica, C.byref(E), phi.data_ptr() if with_phi else None), "energy")
         return (E.value, phi) if with_phi else E.value
 
     def delta_energy(self, i, r_new):
@@ -222,13 +222,13 @@ class Tree:
         _check(lib().bhmc_batch_sweep(self.h, seed, n_sweeps, step, 1 if use_graph else 0, st), "batch_sweep")
         return [s.as_dict() for s in st]
 
-    def energy_grad(self):
+    def energy_grad(self, replica=0):
         torch = _torch()
-        n = self.n_per[0]
+        n = self.n_per[replica]
         g = torch.empty((n, 3), dtype=torch.float64, device=self.device)
         gq = torch.empty(n, dtype=torch.float64, device=self.device)
         E = C.c_double()
-        _check(lib().bhmc_energy_grad(self.h, g.data_ptr(), gq.data_ptr(), C.byref(E)), "energy_grad")
+        _check(lib().bhmc_energy_grad(self.h, replica, g.data_ptr(), gq.data_ptr(), C.byref(E)), "energy_grad")
         return E.value, g, gq
 
     def state(self, replica=0):

@@ -110,6 +110,7 @@ struct bhmc_tree {
     long long* sweep_add = nullptr;  // n_r per replica
     bhmc::MoveIO* io = nullptr;
     double* eterm = nullptr; int eterm_n = 0;
+    char* gwork = nullptr; size_t gwork_bytes = 0;  // gradient workspace
     double* scalar = nullptr;
     int mc_grid = 1;
     hipGraph_t graph = nullptr;
@@ -222,7 +223,7 @@ struct Carver {
 
 static size_t phase1_bytes(int nsrc) {
     size_t b = 0;
-    b += align_up(32 * (size_t)nsrc); b += 2 * align_up(8 * (size_t)nsrc); b += 4 * align_up(4 * (size_t)nsrc);
+    b += align_up(32 * (size_t)nsrc); b += 3 * align_up(8 * (size_t)nsrc); b += 2 * align_up(4 * (size_t)nsrc);
     return b;
 }
 
@@ -234,7 +235,8 @@ static bhmc_status alloc_phase1(bhmc_tree* t, int r) {
     h.src = c.take<double4>(h.nsrc);
     h.keys = c.take<uint64_t>(h.nsrc); h.ktmp = c.take<uint64_t>(h.nsrc);
     h.perm = c.take<int>(h.nsrc); h.ptmp = c.take<int>(h.nsrc);
-    h.leaf_of = c.take<int>(h.nsrc); h.slot_of = c.take<int>(h.nsrc);
+    h.track = c.take<int2>(h.nsrc);
+    if (c.off > phase1_bytes(h.nsrc)) return fail(BHMC_EINTERNAL, "source arena carved past its allocation");
     return BHMC_OK;
 }
 
@@ -242,18 +244,20 @@ static bhmc_status alloc_phase2(bhmc_tree* t, int r) {
     Rep& h = t->host[r];
     if (t->arena2[r]) { hipFree(t->arena2[r]); t->arena2[r] = nullptr; }
     const size_t nc = h.ncell, nl = h.nleaf, np = h.pool;
-    size_t b = align_up(32 * nc) + 6 * align_up(4 * nc) + align_up(8 * nc) +
+    size_t b = align_up(32 * nc) + align_up(16 * nc) + 4 * align_up(4 * nc) + align_up(8 * nc) +
                align_up(8 * nc * (size_t)t->mstride) + 3 * align_up(4 * nl) + align_up(32 * np) +
                align_up(4 * np);
     HIP_TRY(hipMalloc(&t->arena2[r], b));
     Carver c{(char*)t->arena2[r]};
+    const size_t cap_bytes = b;
     h.cgeo = c.take<double4>(nc);
-    h.clink = c.take<int>(nc); h.ccount = c.take<int>(nc); h.cparent = c.take<int>(nc);
+    h.cm = c.take<int4>(nc); h.cparent = c.take<int>(nc);
     h.clevel = c.take<int>(nc); h.cbegin = c.take<int>(nc); h.cend = c.take<int>(nc);
     h.ckey = c.take<uint64_t>(nc);
     h.M = c.take<double>(nc * (size_t)t->mstride);
     h.lcell = c.take<int>(nl); h.lbase = c.take<int>(nl); h.lcap = c.take<int>(nl);
     h.pool4 = c.take<double4>(np); h.pidx = c.take<int>(np);
+    if (c.off > cap_bytes) return fail(BHMC_EINTERNAL, "tree arena carved past its allocation");
     return BHMC_OK;
 }
 
@@ -326,7 +330,7 @@ static void destroy(bhmc_tree* t) {
     for (void* p : t->arena1) if (p) hipFree(p);
     for (void* p : t->arena2) if (p) hipFree(p);
     hipFree(t->reps); hipFree(t->queue); hipFree(t->list_all); hipFree(t->list_one);
-    hipFree(t->sweep_add); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar);
+    hipFree(t->sweep_add); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar); hipFree(t->gwork);
     if (t->host) hipHostFree(t->host);
     if (t->pin) hipHostFree(t->pin);
     delete t;
@@ -438,29 +442,73 @@ extern "C" bhmc_status bhmc_rebuild(bhmc_tree* tree, int32_t replica) {
     return rebuild_one(tree, replica);
 }
 
-extern "C" bhmc_status bhmc_energy(bhmc_tree* t, double* E_host, double* phi_dev) {
-    bhmc_status st = check_rep(t, 0);
-    if (st) return st;
-    const int n = t->host[0].n;
+static bhmc_status ensure_eterm(bhmc_tree* t, int n) {
     if (t->eterm_n < n) {
         hipFree(t->eterm);
         t->eterm = nullptr;
+        t->eterm_n = 0;
         HIP_TRY(hipMalloc(&t->eterm, sizeof(double) * n));
         t->eterm_n = n;
     }
-    t->ops->energy(t->stream, t->reps, 0, n, phi_dev, t->eterm);
-    bhmc::launch_sum(t->stream, t->eterm, n, t->host[0].l_B, t->scalar);
+    return BHMC_OK;
+}
+
+// Sum of the per-ion energy terms; a NaN there marks a failed traversal.
+static bhmc_status finish_energy(bhmc_tree* t, int r, int n, double* E_host, const char* what) {
+    bhmc::launch_sum(t->stream, t->eterm, n, t->host[r].l_B, t->scalar);
     HIP_TRY(hipGetLastError());
     double E = 0.0;
-    if ((st = d2h(t, &E, t->scalar, sizeof(double)))) return st;
+    bhmc_status st = d2h(t, &E, t->scalar, sizeof(double));
+    if (st) return st;
     if (std::isnan(E)) {
         if ((st = download(t))) return st;
-        const int d = t->host[0].err_detail;
-        if (d > 1) return fail(BHMC_EINTERNAL, "device index check %d failed in the energy traversal", d);
+        const int d = t->host[r].err_detail;
+        if (d > 1) return fail(BHMC_EINTERNAL, "device index check %d failed in the %s traversal", d, what);
         return fail(BHMC_ESTACK, "a traversal list outgrew its LDS capacity");
     }
     if (E_host) *E_host = E;
     return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_energy(bhmc_tree* t, int32_t replica, double* E_host, double* phi_dev) {
+    bhmc_status st = check_rep(t, replica);
+    if (st) return st;
+    const int n = t->host[replica].n;
+    if ((st = ensure_eterm(t, n))) return st;
+    t->ops->energy(t->stream, t->reps, replica, n, phi_dev, t->eterm);
+    HIP_TRY(hipGetLastError());
+    return finish_energy(t, replica, n, E_host, "energy");
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* dEdr_dev, double* dEdq_dev,
+                                        double* E_host) {
+    bhmc_status st = check_rep(t, replica);
+    if (st) return st;
+    if (!dEdr_dev || !dEdq_dev) return fail(BHMC_EINVAL, "null gradient output");
+    if (!t->ops->grad) return fail(BHMC_EINVAL, "gradient not available for p = %d", t->p);
+    const Rep& h = t->host[replica];
+    const int n = h.n;
+    if ((st = ensure_eterm(t, n))) return st;
+    const size_t lb = align256(sizeof(double) * (size_t)h.ncell * t->mstride);
+    const size_t gb = align256(sizeof(double) * 4 * (size_t)h.nsrc);
+    const size_t tb = align256(sizeof(double) * 4 * (size_t)n);
+    if (t->gwork_bytes < lb + gb + tb) {
+        hipFree(t->gwork);
+        t->gwork = nullptr;
+        t->gwork_bytes = 0;
+        HIP_TRY(hipMalloc(&t->gwork, lb + gb + tb));
+        t->gwork_bytes = lb + gb + tb;
+    }
+    bhmc::GradWork w;
+    w.L = (double*)t->gwork;
+    w.G = (double4*)(t->gwork + lb);
+    w.Gt = (double4*)(t->gwork + lb + gb);
+    w.ncell = h.ncell; w.nsrc = h.nsrc; w.n = n;
+    t->ops->grad(t->stream, t->reps, replica, w, dEdr_dev, dEdq_dev, t->eterm);
+    HIP_TRY(hipGetLastError());
+    return finish_energy(t, replica, n, E_host, "gradient");
 }
 
 static bhmc_status run_move(bhmc_tree* t, int64_t i, const double* r_new, int mode, bhmc::MoveIO& io) {
@@ -633,14 +681,6 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
     return BHMC_OK;
 }
 
-extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, double* dEdr_dev, double* dEdq_dev, double* E_host) {
-    bhmc_status st = check_rep(t, 0);
-    if (st) return st;
-    if (!t->ops->grad) return fail(BHMC_EINVAL, "gradient not available");
-    (void)dEdr_dev; (void)dEdq_dev; (void)E_host;
-    return fail(BHMC_EINVAL, "gradient not available");
-}
-
 extern "C" bhmc_status bhmc_get_state(bhmc_tree* t, int32_t r, double* x, double* y, double* z, double* q) {
     bhmc_status st = check_rep(t, r);
     if (st) return st;
@@ -670,8 +710,14 @@ extern "C" bhmc_status bhmc_get_cells(bhmc_tree* t, int32_t r, int32_t* level, u
     const size_t nc = h.ncell;
     if (level && (st = d2h(t, level, h.clevel, 4 * nc))) return st;
     if (kmin && (st = d2h(t, kmin, h.ckey, 8 * nc))) return st;
-    if (count && (st = d2h(t, count, h.ccount, 4 * nc))) return st;
-    if (link && (st = d2h(t, link, h.clink, 4 * nc))) return st;
+    if (count || link) {
+        std::vector<int4> cm(nc);
+        if ((st = d2h(t, cm.data(), h.cm, 16 * nc))) return st;
+        for (size_t c = 0; c < nc; ++c) {
+            if (count) count[c] = cm[c].x;
+            if (link) link[c] = cm[c].y;
+        }
+    }
     if (geo && (st = d2h(t, geo, h.cgeo, 32 * nc))) return st;
     if (moments) {
         std::vector<double> rows(nc * (size_t)t->mstride);

@@ -203,7 +203,7 @@ k_topology(Rep* reps, const int* rep_list) {
     const uint64_t* keys = R.keys;
     if (threadIdx.x == 0) {
         R.ckey[0] = 0; R.clevel[0] = 0; R.cparent[0] = -1; R.cbegin[0] = 0; R.cend[0] = n;
-        R.ccount[0] = n;
+        R.cm[0] = make_int4(n, -1, -1, 0);
         double4 g; cell_geometry(R, 0, 0, g); R.cgeo[0] = g;
         R.level_start[0] = 0;
         s_next = 1; s_leaf = 0;
@@ -228,7 +228,7 @@ k_topology(Rep* reps, const int* rep_list) {
                 R.status = -5;  // the counting pass and this pass disagree: write nothing
             } else if (valid && split) {
                 const int first = next0 + 8 * (int)(ex & 0xffffffffu);
-                R.clink[c] = first;
+                R.cm[c].y = first;
                 const uint64_t pk = R.ckey[c];
                 const int csh = 60 - 3 * level;
                 int cb = b;
@@ -237,7 +237,8 @@ k_topology(Rep* reps, const int* rep_list) {
                     const int ce = (d == 7) ? e : lower_bound_key(keys, cb, e, pk | ((uint64_t)(d + 1) << csh));
                     const int ch = first + d;
                     R.ckey[ch] = ck; R.clevel[ch] = level + 1; R.cparent[ch] = c;
-                    R.cbegin[ch] = cb; R.cend[ch] = ce; R.ccount[ch] = ce - cb;
+                    R.cbegin[ch] = cb; R.cend[ch] = ce;
+                    R.cm[ch] = make_int4(ce - cb, -1, -1, 0);
                     double4 g; cell_geometry(R, level + 1, ck, g); R.cgeo[ch] = g;
                     cb = ce;
                 }
@@ -245,10 +246,11 @@ k_topology(Rep* reps, const int* rep_list) {
                 R.status = -5;
             } else if (valid) {
                 const int leaf = leaf0 + (int)(ex >> 32);
-                R.clink[c] = -1 - leaf;
                 R.lcell[leaf] = c;
                 const int cnt = e - b;
-                R.lcap[leaf] = R.slack * (cnt > R.leaf_cap ? cnt : R.leaf_cap) + 2;
+                const int cap = R.slack * (cnt > R.leaf_cap ? cnt : R.leaf_cap) + 2;
+                R.lcap[leaf] = cap;
+                R.cm[c] = make_int4(cnt, -1 - leaf, -1, cap);
             }
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -299,13 +301,13 @@ k_leaves(Rep* reps, const int* rep_list) {
         if (c < 0 || c >= R.ncell) { R.status = -8; continue; }
         const int b = R.cbegin[c], e = R.cend[c], base = R.lbase[l];
         if (b < 0 || e > R.nsrc || b > e || base + (e - b) > R.pool) { R.status = -8; continue; }
+        R.cm[c].z = base;
         for (int k = b; k < e; ++k) {
             const int s = R.perm[k];
             if (s < 0 || s >= R.nsrc) { R.status = -8; continue; }
             R.pool4[base + k - b] = R.src[s];
             R.pidx[base + k - b] = s;
-            R.leaf_of[s] = l;
-            R.slot_of[s] = k - b;
+            R.track[s] = make_int2(c, k - b);
         }
     }
 }
@@ -331,7 +333,7 @@ k_p2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
         if (c < 0 || c >= R.ncell) continue;
         const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
         const double4 g = R.cgeo[c];
-        const int base = R.lbase[l], cnt = R.ccount[c];
+        const int base = R.lbase[l], cnt = R.cm[c].x;
         if (cnt < 0 || base < 0 || base + cnt > R.pool) continue;
         double acc = 0.0;
         for (int j = 0; j < cnt; ++j) {
@@ -359,7 +361,7 @@ k_m2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
         const long long items = (long long)(le - ls) * nterms;
         for (long long it = threadIdx.x; it < items; it += blockDim.x) {
             const int c = ls + (int)(it / nterms), k = (int)(it % nterms);
-            const int first = R.clink[c];
+            const int first = R.cm[c].y;
             if (first < 0 || first + 8 > R.ncell) continue;
             const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
             const double hc = R.cgeo[c].w * 0.5;

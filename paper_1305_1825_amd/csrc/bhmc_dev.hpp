@@ -42,10 +42,10 @@ struct Rep {
     double4* src;                  // (x, y, z, q) per source, home copy
     uint64_t* keys; int* perm;     // sorted keys and source index, as built
     uint64_t* ktmp; int* ptmp;     // radix-sort ping-pong
-    int* leaf_of; int* slot_of;    // tracking: leaf and slot of each source
+    int2* track;                   // tracking of each source: (its leaf's cell, slot)
     double4* cgeo;                 // centre x, y, z and half side h
-    int* clink;                    // first child (>= 0) or -1 - leaf
-    int* ccount;                   // N_A
+    int4* cm;                      // (N_A, link, leaf slot base, leaf capacity); link is the
+                                   // first child (>= 0) or -1 - leaf; base/cap only for leaves
     int* cparent; int* clevel;
     uint64_t* ckey;                // smallest key of the cell
     int* cbegin; int* cend;        // build range in the sorted order

@@ -20,6 +20,8 @@
 #include "bhmc_dev.hpp"
 #include "bhmc_internal.hpp"
 
+#include <algorithm>
+
 #ifndef BHMC_P
 #error "compile once per expansion order with -DBHMC_P=<p>"
 #endif
@@ -42,12 +44,15 @@ constexpr int cmindex(int n1, int n2, int n3) {
 }
 
 struct TEnt { int n1, n2, n3, s, x1, y1, z1, x2, y2, z2; };
-struct TTab { TEnt e[NTERM]; };
+template <int N>
+struct TTab { TEnt e[N]; };
 
-constexpr TTab make_tab() {
-    TTab t{};
+// entries of every multi-index up to order PP, in the graded order above
+template <int PP>
+constexpr TTab<(PP + 1) * (PP + 2) * (PP + 3) / 6> make_tab() {
+    TTab<(PP + 1) * (PP + 2) * (PP + 3) / 6> t{};
     int k = 0;
-    for (int s = 0; s <= P; ++s)
+    for (int s = 0; s <= PP; ++s)
         for (int n1 = s; n1 >= 0; --n1)
             for (int n2 = s - n1; n2 >= 0; --n2) {
                 const int n3 = s - n1 - n2;
@@ -63,7 +68,11 @@ constexpr TTab make_tab() {
             }
     return t;
 }
-constexpr TTab TT = make_tab();
+constexpr auto TT = make_tab<P>();
+// one order more for the field, dT_n/dR_k = (n_k + 1) T_{n + e_k}; the first
+// NTERM entries coincide with TT
+constexpr int NTERM1 = (P + 2) * (P + 3) * (P + 4) / 6;
+constexpr auto TT1 = make_tab<P + 1>();
 
 struct MiTab { int v[3 * NTERM]; };
 constexpr MiTab make_mi() {
@@ -85,26 +94,29 @@ __device__ __forceinline__ double mono(int k, double dx, double dy, double dz) {
 
 // ------------------------------------------------------------ far field
 // T_n(R) by eq. 3.4 with T_0 = 1/|R|:
-//   T_n = -[ (2s-1)/s sum_i R_i T_{n-e_i} + (s-1)/s sum_i T_{n-2e_i} ] / |R|^2,
-// accumulated into sum_n T_n M^n as soon as each T_n exists.
+//   T_n = -[ (2s-1)/s sum_i R_i T_{n-e_i} + (s-1)/s sum_i T_{n-2e_i} ] / |R|^2.
+template <int K, int N>
+__device__ __forceinline__ void t_step(double (&T)[N], double Rx, double Ry, double Rz, double ir2) {
+    constexpr TEnt e = TT1.e[K];
+    double f = 0.0, g = 0.0;
+    if constexpr (e.x1 >= 0) f = Rx * T[e.x1];
+    if constexpr (e.y1 >= 0) f = fma(Ry, T[e.y1], f);
+    if constexpr (e.z1 >= 0) f = fma(Rz, T[e.z1], f);
+    if constexpr (e.x2 >= 0) g = T[e.x2];
+    if constexpr (e.y2 >= 0) g += T[e.y2];
+    if constexpr (e.z2 >= 0) g += T[e.z2];
+    constexpr double A = (2.0 * e.s - 1.0) / e.s;
+    constexpr double B = (e.s - 1.0) / e.s;
+    if constexpr (e.s >= 2) T[K] = -fma(A, f, B * g) * ir2;
+    else T[K] = -(A * f) * ir2;
+}
+
+// sum_n T_n M^n, each T_n folded into the sum as soon as it exists
 template <int K>
 __device__ __forceinline__ void far_rec(double (&T)[NTERM], double Rx, double Ry, double Rz,
                                         double ir2, const double* __restrict__ Mc, double& acc) {
     if constexpr (K < NTERM) {
-        constexpr TEnt e = TT.e[K];
-        if constexpr (K > 0) {
-            double f = 0.0, g = 0.0;
-            if constexpr (e.x1 >= 0) f = Rx * T[e.x1];
-            if constexpr (e.y1 >= 0) f = fma(Ry, T[e.y1], f);
-            if constexpr (e.z1 >= 0) f = fma(Rz, T[e.z1], f);
-            if constexpr (e.x2 >= 0) g = T[e.x2];
-            if constexpr (e.y2 >= 0) g += T[e.y2];
-            if constexpr (e.z2 >= 0) g += T[e.z2];
-            constexpr double A = (2.0 * e.s - 1.0) / e.s;
-            constexpr double B = (e.s - 1.0) / e.s;
-            if constexpr (e.s >= 2) T[K] = -fma(A, f, B * g) * ir2;
-            else T[K] = -(A * f) * ir2;
-        }
+        if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
         acc = fma(T[K], Mc[K], acc);
         far_rec<K + 1>(T, Rx, Ry, Rz, ir2, Mc, acc);
     }
@@ -120,6 +132,70 @@ __device__ __forceinline__ double far_eval(double Rx, double Ry, double Rz, cons
     return acc;
 }
 
+// ------------------------------------------------------------ far field, gradient form
+// One (target, far cell) pair of the exact gradient of the treecode energy.
+// With R = c - x and P(x) = sum_n T_n(R) M^n (eq. 3.3), the target side needs
+//   P   and   F_k = sum_m m_k T_m M^{m - e_k} = -dP/dx_k,
+// which takes T up to order p + 1.  The source side, sum_n T_n (y - c)^n per
+// member y, is carried by the cell's adjoint coefficients L^n += w T_n (n of
+// order <= p), added with device-wide atomics.
+template <int K>
+__device__ __forceinline__ void far_rec_grad(double (&T)[NTERM1], double Rx, double Ry, double Rz,
+                                             double ir2, const double* __restrict__ Mc,
+                                             double* __restrict__ Lc, double w, double& phi,
+                                             double& fx, double& fy, double& fz) {
+    if constexpr (K < NTERM1) {
+        constexpr TEnt e = TT1.e[K];
+        if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
+        if constexpr (K < NTERM) {
+            phi = fma(T[K], Mc[K], phi);
+            unsafeAtomicAdd(Lc + K, w * T[K]);
+        }
+        if constexpr (e.x1 >= 0) fx = fma((double)e.n1 * T[K], Mc[e.x1], fx);
+        if constexpr (e.y1 >= 0) fy = fma((double)e.n2 * T[K], Mc[e.y1], fy);
+        if constexpr (e.z1 >= 0) fz = fma((double)e.n3 * T[K], Mc[e.z1], fz);
+        far_rec_grad<K + 1>(T, Rx, Ry, Rz, ir2, Mc, Lc, w, phi, fx, fy, fz);
+    }
+}
+
+// Polynomial sum_n C_n d^n and its gradient sum_n C_n n_k d^{n - e_k} for
+// coefficients C that are either stored (STORED, in Cc) or T_n(R) computed
+// on the fly.  The monomials d^n are built by the same graded
+// recurrence, each from one of order |n| - 1.
+template <int K, bool STORED>
+__device__ __forceinline__ void poly_rec(double (&T)[NTERM], double (&D)[NTERM], double Rx, double Ry,
+                                         double Rz, double ir2, double dx, double dy, double dz,
+                                         const double* __restrict__ Cc, double& v, double& gx,
+                                         double& gy, double& gz) {
+    if constexpr (K < NTERM) {
+        constexpr TEnt e = TT.e[K];
+        double c;
+        if constexpr (STORED) {
+            c = Cc[K];
+        } else {
+            if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
+            c = T[K];
+        }
+        if constexpr (K == 0) D[0] = 1.0;
+        else if constexpr (e.n1 >= 1) D[K] = D[e.x1] * dx;
+        else if constexpr (e.n2 >= 1) D[K] = D[e.y1] * dy;
+        else D[K] = D[e.z1] * dz;
+        v = fma(c, D[K], v);
+        if constexpr (e.x1 >= 0) gx = fma((double)e.n1 * c, D[e.x1], gx);
+        if constexpr (e.y1 >= 0) gy = fma((double)e.n2 * c, D[e.y1], gy);
+        if constexpr (e.z1 >= 0) gz = fma((double)e.n3 * c, D[e.z1], gz);
+        poly_rec<K + 1, STORED>(T, D, Rx, Ry, Rz, ir2, dx, dy, dz, Cc, v, gx, gy, gz);
+    }
+}
+
+// Where the per-source gradient goes: G[s] = (dE/dx, dE/dy, dE/dz, dE/dq) of
+// source s through its role as a source; L: adjoint coefficients per cell.
+struct GradOut {
+    double* L;
+    double4* G;
+    double half_lB;
+};
+
 // ------------------------------------------------------------ traversal state
 constexpr uint32_t kCellMask = 0xFFFFFFu;
 constexpr uint32_t kFlagIon = 1u << 28, kFlagImg = 1u << 29, kFlagDirect = 1u << 30;
@@ -128,7 +204,12 @@ __device__ __forceinline__ uint32_t pack(int cell, int t, uint32_t flags) {
     return (uint32_t)cell | ((uint32_t)t << 24) | flags;
 }
 
-template <int NTG, int BLOCK>
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <int NTG, int BLOCK, int NV = 1>
 struct Trav {
     static constexpr int FCAP = 4096;
     static constexpr int FARCAP = 1024 + BLOCK;
@@ -138,8 +219,8 @@ struct Trav {
     uint32_t front[2][FCAP];
     uint32_t farl[FARCAP];
     uint32_t nearl[NEARCAP];
-    int near_pre[NEARCAP + 1];
     int near_base[NEARCAP];
+    int near_pre[NEARCAP + 1];       // slot counts, then their exclusive prefix
     uint32_t flagl[2 * NTG];
     double Mx[2 * NTG][MSTR];
     double tx[NTG], ty[NTG], tz[NTG];
@@ -149,9 +230,10 @@ struct Trav {
     uint32_t ovl[OVLCAP];
     int n_ovl, ovl_t, ovl_ex;
     int err, overlap, coincide;
+    uint64_t wcnt[2][NW];            // per-wave packed list counts, double buffered
     uint64_t wsum[NW + 1];
-    double red[NW][NTG];
-    double res[NTG];
+    double red[NW][NTG * NV];
+    double res[NTG * NV];            // per target: potential, or (potential, F_x, F_y, F_z)
 };
 
 template <int NTG>
@@ -161,45 +243,79 @@ __device__ __forceinline__ void add_to(double (&acc)[NTG], int t, double v) {
         if (k == t) acc[k] += v;
 }
 
-template <int NTG, int BLOCK>
-__device__ void flush_far(const Rep& R, Trav<NTG, BLOCK>& S, int far_n, double (&acc)[NTG]) {
-    for (int j = threadIdx.x; j < far_n; j += BLOCK) {
-        const uint32_t e = S.farl[j];
+template <int NTG4>
+__device__ __forceinline__ void add_to4(double (&acc)[NTG4], int t, double v0, double v1, double v2,
+                                        double v3) {
+#pragma unroll
+    for (int k = 0; k < NTG4 / 4; ++k)
+        if (k == t) { acc[4 * k] += v0; acc[4 * k + 1] += v1; acc[4 * k + 2] += v2; acc[4 * k + 3] += v3; }
+}
+
+// Far cells, plus (index >= far_n) the cells holding an excluded source whose
+// corrected moments sit in LDS.  Gradient form (NV = 4): the target side is
+// accumulated per target, the source side goes to the cell's adjoint
+// coefficients.
+template <int NTG, int BLOCK, int NV>
+__device__ __forceinline__ void far_pass(const Rep& R, Trav<NTG, BLOCK, NV>& S, int far_n, int nflag,
+                                         double (&acc)[NTG * NV], const GradOut* go) {
+    for (int j = threadIdx.x; j < far_n + nflag; j += BLOCK) {
+        const bool fl = j >= far_n;
+        const uint32_t e = fl ? S.flagl[j - far_n] : S.farl[j];
         const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
         if (c >= R.ncell) { S.err = kErrFarCell; continue; }
         const double4 g = R.cgeo[c];
-        const double* Mc = (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32);
-        add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], Mc));
+        const double* Mc = fl ? S.Mx[j - far_n]
+                              : (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32);
+        const double Rx = g.x - S.tx[t], Ry = g.y - S.ty[t], Rz = g.z - S.tz[t];
+        if constexpr (NV == 1) {
+            add_to<NTG>(acc, t, far_eval(Rx, Ry, Rz, Mc));
+        } else {
+            const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+            double T[NTERM1];
+            T[0] = rsqrt_nr(r2);
+            const double ir2 = T[0] * T[0];
+            const double w = go->half_lB * S.es_i[t].w;
+            double phi = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+            far_rec_grad<0>(T, Rx, Ry, Rz, ir2, Mc, go->L + (size_t)c * MSTR, w, phi, fx, fy, fz);
+            add_to4<NTG * NV>(acc, t, phi, fx, fy, fz);
+        }
     }
 }
 
-// Near leaves: direct sum over the leaf's index array (slot order).  For the
-// overlap target every ion other than the mover within tau is an overlap.
-template <int NTG, int BLOCK>
-__device__ void flush_near(const Rep& R, Trav<NTG, BLOCK>& S, int near_n, double (&acc)[NTG]) {
-    for (int j = threadIdx.x; j < near_n; j += BLOCK) {
-        const uint32_t e = S.nearl[j];
-        const int c = (int)(e & kCellMask);
-        int base = 0, cnt = 0;
-        if (c < R.ncell) {
-            const int leaf = -1 - R.clink[c];
-            if (leaf >= 0 && leaf < R.nleaf) {
-                base = R.lbase[leaf];
-                cnt = R.ccount[c];
-                if (cnt < 0 || cnt > R.lcap[leaf] || base < 0 || base + cnt > R.pool) {
-                    S.err = kErrNearSlots;
-                    cnt = 0;
-                }
-            } else {
-                S.err = kErrNearLeaf;
-            }
-        } else {
-            S.err = kErrNearLeaf;
-        }
-        S.near_base[j] = base;
-        S.near_pre[j] = cnt;
+// Gradient form: the adjoint coefficients of a flagged far cell also act on
+// the excluded sources inside it, which take no part in the target's
+// interactions; their pair terms w q_e sum_n T_n (y_e - c)^n are taken back
+// out of G here (one lane per (flagged cell, excluded source)).
+template <int NTG, int BLOCK, int NV>
+__device__ void flag_corrections(const Rep& R, Trav<NTG, BLOCK, NV>& S, int nflag, const GradOut* go) {
+    for (int j = threadIdx.x; j < 2 * nflag; j += BLOCK) {
+        const uint32_t e = S.flagl[j >> 1];
+        const int x = j & 1;
+        if (!(e & (x ? kFlagImg : kFlagIon))) continue;
+        const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
+        if (c >= R.ncell) { S.err = kErrFlagCell; continue; }
+        const double4 es = x ? S.es_k[t] : S.es_i[t];
+        const int sid = x ? S.ex_k[t] : S.ex_i[t];
+        if (sid < 0 || sid >= R.nsrc) { S.err = kErrFlagCell; continue; }
+        const double4 g = R.cgeo[c];
+        const double Rx = g.x - S.tx[t], Ry = g.y - S.ty[t], Rz = g.z - S.tz[t];
+        double T[NTERM], D[NTERM];
+        T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
+        const double ir2 = T[0] * T[0];
+        double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        poly_rec<0, false>(T, D, Rx, Ry, Rz, ir2, es.x - g.x, es.y - g.y, es.z - g.z, nullptr, v, gx, gy, gz);
+        const double w = go->half_lB * S.es_i[t].w;
+        double4* G = go->G + sid;
+        unsafeAtomicAdd(&G->x, -w * es.w * gx);
+        unsafeAtomicAdd(&G->y, -w * es.w * gy);
+        unsafeAtomicAdd(&G->z, -w * es.w * gz);
+        unsafeAtomicAdd(&G->w, -w * v);
     }
-    __syncthreads();
+}
+
+// Exclusive scan of the near leaves' slot counts (in place in near_pre).
+template <int NTG, int BLOCK, int NV>
+__device__ int near_scan(Trav<NTG, BLOCK, NV>& S, int near_n) {
     int carry = 0;
     for (int base = 0; base < near_n; base += BLOCK) {
         const int j = base + threadIdx.x;
@@ -210,7 +326,15 @@ __device__ void flush_near(const Rep& R, Trav<NTG, BLOCK>& S, int near_n, double
         carry += (int)tot;
         __syncthreads();
     }
-    const int total = carry;
+    return carry;
+}
+
+// Near leaves: direct sum over each leaf's index array in slot order.  For
+// the overlap target, every ion other than the mover within tau is an overlap.
+// Gradient form: the pair term w q_j / |x - y_j| also goes to source j.
+template <int NTG, int BLOCK, int NV>
+__device__ __forceinline__ void near_pass(const Rep& R, Trav<NTG, BLOCK, NV>& S, int near_n, int total,
+                                          double (&acc)[NTG * NV], const GradOut* go) {
     const int n_ion = R.n;
     for (int f = threadIdx.x; f < total; f += BLOCK) {
         int lo = 0, hi = near_n - 1;  // last j with near_pre[j] <= f
@@ -224,7 +348,7 @@ __device__ void flush_near(const Rep& R, Trav<NTG, BLOCK>& S, int near_n, double
         const double4 s = R.pool4[slot];
         const bool check_ovl = (t == S.ovl_t);
         int sid = -1;
-        if ((e & (kFlagIon | kFlagImg)) || check_ovl) {
+        if ((e & (kFlagIon | kFlagImg)) || check_ovl || NV > 1) {
             sid = R.pidx[slot];
             if (((e & kFlagIon) && sid == S.ex_i[t]) || ((e & kFlagImg) && sid == S.ex_k[t])) continue;
         }
@@ -232,9 +356,21 @@ __device__ void flush_near(const Rep& R, Trav<NTG, BLOCK>& S, int near_n, double
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (check_ovl && sid < n_ion && sid != S.ovl_ex && d2 <= R.tau2) S.overlap = 1;
         if (d2 == 0.0) { S.coincide = 1; continue; }
-        add_to<NTG>(acc, t, s.w * rsqrt_nr(d2));
+        if constexpr (NV == 1) {
+            add_to<NTG>(acc, t, s.w * rsqrt_nr(d2));
+        } else {
+            if (sid < 0 || sid >= R.nsrc) { S.err = kErrNearSlots; continue; }
+            const double ir = rsqrt_nr(d2);
+            const double qi3 = s.w * (ir * ir * ir);
+            add_to4<NTG * NV>(acc, t, s.w * ir, qi3 * dx, qi3 * dy, qi3 * dz);
+            const double w = go->half_lB * S.es_i[t].w;
+            double4* G = go->G + sid;
+            unsafeAtomicAdd(&G->x, w * qi3 * dx);
+            unsafeAtomicAdd(&G->y, w * qi3 * dy);
+            unsafeAtomicAdd(&G->z, w * qi3 * dz);
+            unsafeAtomicAdd(&G->w, w * ir);
+        }
     }
-    __syncthreads();
 }
 
 // squared distance from a point to the closed cube of centre g and half side g.w
@@ -246,95 +382,112 @@ __device__ __forceinline__ double box_dist2(double4 g, double x, double y, doubl
 
 // Hard-core check below cells the traversal took as far: descend every cell
 // whose cube comes within tau (plus a rounding margin) of the target.
-template <int NTG, int BLOCK>
-__device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK>& S) {
-    __shared__ int s_cnt[2];
+template <int NTG, int BLOCK, int NV>
+__device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK, NV>& S, int* cnt2) {
+    using TS = Trav<NTG, BLOCK, NV>;
     const int t = S.ovl_t;
     const double x = S.tx[t], y = S.ty[t], z = S.tz[t];
     const double reach = sqrt(R.tau2) + 1e-12 * R.side;
     const double reach2 = reach * reach;
     // n_ovl counts every insert attempt; entries past OVLCAP were never stored
-    int cur = 0, fs = S.n_ovl < Trav<NTG, BLOCK>::OVLCAP ? S.n_ovl : Trav<NTG, BLOCK>::OVLCAP;
+    int cur = 0, fs = S.n_ovl < TS::OVLCAP ? S.n_ovl : TS::OVLCAP;
     for (int j = threadIdx.x; j < fs; j += BLOCK) S.front[0][j] = S.ovl[j];
     while (fs > 0) {
-        if (threadIdx.x == 0) s_cnt[cur ^ 1] = 0;
+        if (threadIdx.x == 0) cnt2[cur ^ 1] = 0;
         __syncthreads();
         for (int j = threadIdx.x; j < fs; j += BLOCK) {
             const int c = (int)S.front[cur][j];
             if (c < 0 || c >= R.ncell) { S.err = kErrOvlLeaf; continue; }
-            const int link = R.clink[c];
-            if (link >= 0 && link + 8 > R.ncell) { S.err = kErrChildLink; continue; }
-            if (link < 0) {
-                const int leaf = -1 - link;
-                if (leaf >= R.nleaf) { S.err = kErrOvlLeaf; continue; }
-                const int base = R.lbase[leaf], cnt = R.ccount[c];
-                if (cnt < 0 || base < 0 || base + cnt > R.pool) { S.err = kErrOvlLeaf; continue; }
-                for (int k = 0; k < cnt; ++k) {
-                    const int sid = R.pidx[base + k];
+            const int4 m = R.cm[c];
+            if (m.y >= 0 && m.y + 8 > R.ncell) { S.err = kErrChildLink; continue; }
+            if (m.y < 0) {
+                if (m.x < 0 || m.z < 0 || m.z + m.x > R.pool) { S.err = kErrOvlLeaf; continue; }
+                for (int k = 0; k < m.x; ++k) {
+                    const int sid = R.pidx[m.z + k];
                     if (sid >= R.n || sid == S.ovl_ex) continue;
-                    const double4 s = R.pool4[base + k];
+                    const double4 s = R.pool4[m.z + k];
                     const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
                     if (dx * dx + dy * dy + dz * dz <= R.tau2) S.overlap = 1;
                 }
             } else {
                 for (int d = 0; d < 8; ++d) {
-                    const int ch = link + d;
-                    if (R.ccount[ch] == 0) continue;
+                    const int ch = m.y + d;
+                    if (R.cm[ch].x == 0) continue;
                     if (box_dist2(R.cgeo[ch], x, y, z) <= reach2) {
-                        const int slot = atomicAdd(&s_cnt[cur ^ 1], 1);
-                        if (slot < Trav<NTG, BLOCK>::FCAP) S.front[cur ^ 1][slot] = (uint32_t)ch;
+                        const int slot = atomicAdd(&cnt2[cur ^ 1], 1);
+                        if (slot < TS::FCAP) S.front[cur ^ 1][slot] = (uint32_t)ch;
                         else S.err = kErrStack;
                     }
                 }
             }
         }
         __syncthreads();
-        fs = s_cnt[cur ^ 1];
-        if (fs > Trav<NTG, BLOCK>::FCAP) fs = Trav<NTG, BLOCK>::FCAP;
+        fs = cnt2[cur ^ 1];
+        if (fs > TS::FCAP) fs = TS::FCAP;
         cur ^= 1;
         __syncthreads();
     }
 }
 
-// Breadth-first MAC traversal from the entries already in front[0].  On
-// return S.res[t] holds the potential at target t from every source except
-// the target's excluded ones, S.err is set if an LDS list overflowed, and
+// Breadth-first MAC traversal (Sec. 3.2) from the entries already in
+// front[0].  Each chunk of BLOCK entries is classified lane by lane; wave
+// ballots and one barrier hand out list slots in a fixed order, so every sum
+// below is taken in the same order on every run.  On return S.res[t] holds
+// the potential at target t from every source except the target's excluded
+// ones (NV = 1), or S.res[4t .. 4t+3] holds that potential and the field F
+// of the far-field gradient form (NV = 4, which also sends each pair's
+// source side through go); S.err reports an overflowed list or a failed index check;
 // S.overlap / S.coincide report hard-core hits at the overlap target.
-template <int NTG, int BLOCK, class Hook>
-__device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hook) {
-    using TS = Trav<NTG, BLOCK>;
-    const int tid = threadIdx.x;
-    double acc[NTG];
+// Returns the number of levels processed (hook is called once per level).
+template <int NTG, int BLOCK, int NV, class Hook>
+__device__ int traverse(const Rep& R, Trav<NTG, BLOCK, NV>& S, int nroot, int* cnt2, Hook&& hook,
+                        const GradOut* go = nullptr) {
+    using TS = Trav<NTG, BLOCK, NV>;
+    constexpr int NW = TS::NW;
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    double acc[NTG * NV];
 #pragma unroll
-    for (int k = 0; k < NTG; ++k) acc[k] = 0.0;
-    int cur = 0, fs = nroot, far_n = 0, near_n = 0, nflag = 0;
+    for (int k = 0; k < NTG * NV; ++k) acc[k] = 0.0;
+    int cur = 0, fs = nroot, far_n = 0, near_n = 0, nflag = 0, buf = 0;
     bool failed = false;
     int level = 0;
     for (; fs > 0 && !failed; ++level) {
         hook(level);
         int next_n = 0;
         for (int base = 0; base < fs; base += BLOCK) {
-            if (far_n > TS::FARCAP - BLOCK) { flush_far<NTG, BLOCK>(R, S, far_n, acc); far_n = 0; __syncthreads(); }
-            if (near_n > TS::NEARCAP - BLOCK) { flush_near<NTG, BLOCK>(R, S, near_n, acc); near_n = 0; }
+            if (far_n > TS::FARCAP - BLOCK) {
+                __syncthreads();
+                far_pass<NTG, BLOCK, NV>(R, S, far_n, 0, acc, go);
+                far_n = 0;
+                __syncthreads();
+            }
+            if (near_n > TS::NEARCAP - BLOCK) {
+                __syncthreads();
+                const int total = near_scan<NTG, BLOCK, NV>(S, near_n);
+                near_pass<NTG, BLOCK, NV>(R, S, near_n, total, acc, go);
+                near_n = 0;
+                __syncthreads();
+            }
             const int j = base + tid;
             const bool valid = j < fs;
             const uint32_t e = valid ? S.front[cur][j] : 0u;
             const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
             const int fi = (e & kFlagIon) ? 1 : 0, fk = (e & kFlagImg) ? 1 : 0;
-            int kind = 0, link = 0;
+            int kind = 0;
+            int4 m = make_int4(0, -1, 0, 0);
             uint32_t cdir = e & kFlagDirect;
             if (valid && c >= R.ncell) {
                 S.err = kErrFrontCell;
             } else if (valid) {
-                const int np = R.ccount[c] - fi - fk;
-                link = R.clink[c];
-                if (link >= 0 && link + 8 > R.ncell) {
+                m = R.cm[c];
+                const double4 g = R.cgeo[c];
+                const int np = m.x - fi - fk;
+                if (m.y >= 0 && m.y + 8 > R.ncell) {
                     S.err = kErrChildLink;
                 } else if (np > 0) {
                     if (cdir) {
-                        kind = link >= 0 ? 3 : 2;
+                        kind = m.y >= 0 ? 3 : 2;
                     } else {
-                        const double4 g = R.cgeo[c];
                         const double dx = g.x - S.tx[t], dy = g.y - S.ty[t], dz = g.z - S.tz[t];
                         const double d2 = dx * dx + dy * dy + dz * dz;
                         const bool mac = 3.0 * (g.w * g.w) <= R.theta2 * d2;
@@ -347,9 +500,9 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
                                     if (slot < TS::OVLCAP) S.ovl[slot] = (uint32_t)c; else S.err = kErrStack;
                                 }
                             }
-                        } else if (np > R.n0 && link >= 0) {
+                        } else if (np > R.n0 && m.y >= 0) {
                             kind = 3;
-                        } else if (link < 0) {
+                        } else if (m.y < 0) {
                             kind = 2;
                         } else {
                             kind = 3;
@@ -358,10 +511,21 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
                     }
                 }
             }
-            const uint64_t v = (uint64_t)(kind == 1) | ((uint64_t)(kind == 2) << 16) |
-                               ((uint64_t)(kind == 3) << 32) | ((uint64_t)(kind == 4) << 48);
-            uint64_t tot;
-            const uint64_t ex = block_exscan<BLOCK>(v, S.wsum, tot);
+            const uint64_t lt = lanemask_lt();
+            const uint64_t bf = __ballot(kind == 1), bn = __ballot(kind == 2);
+            const uint64_t bs = __ballot(kind == 3), bg = __ballot(kind == 4);
+            if (lane == 0)
+                S.wcnt[buf][w] = (uint64_t)__popcll(bf) | ((uint64_t)__popcll(bn) << 16) |
+                                 ((uint64_t)__popcll(bs) << 32) | ((uint64_t)__popcll(bg) << 48);
+            __syncthreads();
+            uint64_t before = 0, tot = 0;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint64_t v = S.wcnt[buf][ww];
+                before += ww < w ? v : 0ull;
+                tot += v;
+            }
+            buf ^= 1;
             const int tf = (int)(tot & 0xffff), tn = (int)((tot >> 16) & 0xffff);
             const int ts = (int)((tot >> 32) & 0xffff), tg = (int)(tot >> 48);
             if (next_n + 8 * ts > TS::FCAP || nflag + tg > 2 * NTG) {  // uniform
@@ -369,24 +533,28 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
                 break;
             }
             if (kind == 1) {
-                S.farl[far_n + (int)(ex & 0xffff)] = e;
+                S.farl[far_n + (int)(before & 0xffff) + __popcll(bf & lt)] = e;
             } else if (kind == 2) {
-                S.nearl[near_n + (int)((ex >> 16) & 0xffff)] = e;
+                const int o = near_n + (int)((before >> 16) & 0xffff) + __popcll(bn & lt);
+                S.nearl[o] = e;
+                S.near_base[o] = m.z;
+                S.near_pre[o] = m.x;
+                if (m.x < 0 || m.z < 0 || m.z + m.x > R.pool) { S.near_pre[o] = 0; S.err = kErrNearSlots; }
             } else if (kind == 4) {
-                S.flagl[nflag + (int)(ex >> 48)] = e;
+                S.flagl[nflag + (int)(before >> 48) + __popcll(bg & lt)] = e;
             } else if (kind == 3) {
-                const int o = next_n + 8 * (int)((ex >> 32) & 0xffff);
+                const int o = next_n + 8 * ((int)((before >> 32) & 0xffff) + __popcll(bs & lt));
                 const int dig_i = fi ? key_digit(S.kx_i[t], level + 1) : -1;
                 const int dig_k = fk ? key_digit(S.kx_k[t], level + 1) : -1;
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
                     const uint32_t fl = (d == dig_i ? kFlagIon : 0u) | (d == dig_k ? kFlagImg : 0u) | cdir;
-                    S.front[cur ^ 1][o + d] = pack(link + d, t, fl);
+                    S.front[cur ^ 1][o + d] = pack(m.y + d, t, fl);
                 }
             }
             far_n += tf; near_n += tn; nflag += tg; next_n += 8 * ts;
-            __syncthreads();
         }
+        __syncthreads();  // the next level reads what this one wrote
         cur ^= 1;
         fs = next_n;
     }
@@ -395,123 +563,207 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, Hook&& hoo
         __syncthreads();
         return level;
     }
-    // far cells that hold an excluded source: corrected moments in LDS
-    if (nflag > 0) {
-        for (int it = tid; it < nflag * NTERM; it += BLOCK) {
-            const int f = it / NTERM, k = it % NTERM;
-            const uint32_t e = S.flagl[f];
-            const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
-            if (c >= R.ncell) { S.err = kErrFlagCell; S.Mx[f][k] = 0.0; continue; }
-            const double4 g = R.cgeo[c];
-            double m = R.M[(size_t)c * MSTR + k];
-            if (e & kFlagIon) { const double4 s = S.es_i[t]; m = m - s.w * mono(k, s.x - g.x, s.y - g.y, s.z - g.z); }
-            if (e & kFlagImg) { const double4 s = S.es_k[t]; m = m - s.w * mono(k, s.x - g.x, s.y - g.y, s.z - g.z); }
-            S.Mx[f][k] = m;
-        }
-        __syncthreads();
-        for (int f = tid; f < nflag; f += BLOCK) {
-            const uint32_t e = S.flagl[f];
-            const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
-            if (c >= R.ncell) continue;
-            const double4 g = R.cgeo[c];
-            add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], S.Mx[f]));
-        }
+    // corrected moments of the far cells that hold an excluded source
+    for (int it = tid; it < nflag * NTERM; it += BLOCK) {
+        const int f = it / NTERM, k = it % NTERM;
+        const uint32_t e = S.flagl[f];
+        const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
+        if (c >= R.ncell) { S.err = kErrFlagCell; S.Mx[f][k] = 0.0; continue; }
+        const double4 g = R.cgeo[c];
+        double mk = R.M[(size_t)c * MSTR + k];
+        if (e & kFlagIon) { const double4 s = S.es_i[t]; mk = mk - s.w * mono(k, s.x - g.x, s.y - g.y, s.z - g.z); }
+        if (e & kFlagImg) { const double4 s = S.es_k[t]; mk = mk - s.w * mono(k, s.x - g.x, s.y - g.y, s.z - g.z); }
+        S.Mx[f][k] = mk;
     }
-    flush_far<NTG, BLOCK>(R, S, far_n, acc);
-    flush_near<NTG, BLOCK>(R, S, near_n, acc);  // ends with a barrier
-    if (S.ovl_t >= 0 && S.n_ovl > 0 && S.err == 0) overlap_below_far<NTG, BLOCK>(R, S);
-    const int lane = lane_id(), w = wave_id();
+    const int total = near_scan<NTG, BLOCK, NV>(S, near_n);  // its barriers also publish Mx
+    far_pass<NTG, BLOCK, NV>(R, S, far_n, nflag, acc, go);
+    if constexpr (NV > 1) flag_corrections<NTG, BLOCK, NV>(R, S, nflag, go);
+    near_pass<NTG, BLOCK, NV>(R, S, near_n, total, acc, go);
+    __syncthreads();
+    if (S.ovl_t >= 0 && S.n_ovl > 0 && S.err == 0) overlap_below_far<NTG, BLOCK, NV>(R, S, cnt2);
 #pragma unroll
-    for (int k = 0; k < NTG; ++k) {
-        const double s = wave_sum(acc[k]);
-        if (lane == 0) S.red[w][k] = s;
+    for (int k = 0; k < NTG * NV; ++k) {
+        const double sum = wave_sum(acc[k]);
+        if (lane == 0) S.red[w][k] = sum;
     }
     __syncthreads();
-    if (tid < NTG) {
-        double s = 0.0;
-        for (int ww = 0; ww < TS::NW; ++ww) s += S.red[ww][tid];
-        S.res[tid] = s;
+    if (tid < NTG * NV) {
+        double sum = 0.0;
+        for (int ww = 0; ww < NW; ++ww) sum += S.red[ww][tid];
+        S.res[tid] = sum;
     }
     __syncthreads();
     return level;
 }
 
 // ------------------------------------------------------------ one Monte Carlo move
+constexpr int kMaxPathCells = 4 * kMaxLevels;
+
 struct McShared {
     int path[4][kMaxLevels];  // root paths: ion old, ion new, image old, image new
     int plen[4];
     uint64_t key[4];
     double4 contrib[4];       // (position, charge) of the four contributions
+    // commit state gathered while the traversal runs
+    int2 tr[2];               // tracking (leaf cell, slot) of the ion and of its image
+    int4 lm_old[2];           // (count, link, base, cap) of their leaves
+    int4 lm_new[2];           // same for the leaves of their new positions
+    int last_pidx[2];         // source in the last slot of each old leaf
+    double4 last_pool[2];     // and its (x, y, z, q)
+    int self_pidx[2];         // source found at the tracked slot (must be the mover)
+    int pf_stage[2];
+    // distinct cells of the four root paths with the contributions they take
+    int nlist;
+    int list_cell[kMaxPathCells];
+    int list_mask[kMaxPathCells];   // bit jj: contribution jj applies; bit 4: internal cell
+    double4 list_geo[kMaxPathCells];
     int ok;
-    int err;                  // index-check failure seen while descending or committing
+    int err;
+    int cnt2[2];
 };
 
 struct MoveOut { double dE; int reason; int accepted; int stop; int detail; };
 
 constexpr double kInf = __builtin_huge_val();
 
-// Local modification of Sec. 3.3 for an accepted move: thread 0 moves the ion
-// and then its image between leaf index arrays (delete = last entry fills the
-// hole; add = append) and keeps the leaf counts; the other threads repair the
-// moments and counts of the cells on the four root paths, applying to each
-// cell, in order, the old ion (-), new ion (+), old image (-), new image (+).
+// One stage of the commit prefetch for old source j (0: ion, 1: image).
+__device__ __forceinline__ void prefetch_stage(const Rep& R, McShared& MS, int j, int s) {
+    const int stage = MS.pf_stage[j];
+    if (stage == 0) {
+        const int2 t = R.track[s];
+        MS.tr[j] = t;
+        MS.pf_stage[j] = (t.x >= 0 && t.x < R.ncell) ? 1 : 9;
+    } else if (stage == 1) {
+        const int4 m = R.cm[MS.tr[j].x];
+        MS.lm_old[j] = m;
+        const bool sane = m.y < 0 && m.x >= 1 && m.z >= 0 && m.z + m.x <= R.pool && m.x <= m.w &&
+                          MS.tr[j].y >= 0 && MS.tr[j].y < m.x;
+        MS.pf_stage[j] = sane ? 2 : 9;
+    } else if (stage == 2) {
+        const int4 m = MS.lm_old[j];
+        MS.last_pidx[j] = R.pidx[m.z + m.x - 1];
+        MS.last_pool[j] = R.pool4[m.z + m.x - 1];
+        MS.self_pidx[j] = R.pidx[m.z + MS.tr[j].y];
+        MS.pf_stage[j] = 3;
+    }
+}
+
+// Local modification of Sec. 3.3 for an accepted move.  Thread 0 moves the
+// ion and then its image between leaf index arrays (delete = the last entry
+// fills the hole; add = append) from the state gathered during the
+// traversal; the other threads repair the moments and counts of the distinct
+// cells of the four root paths, applying to each cell, in order, the old ion
+// (-), the new ion (+), the old image (-) and the new image (+).
 template <int BLOCK>
 __device__ void commit(const Rep& R, McShared& MS, int i) {
     const int tid = threadIdx.x;
-    const int nps = R.images ? 4 : 2;
+    const bool imgs = R.images != 0;
     if (tid == 0) {
-        for (int part = 0; part < nps / 2; ++part) {
-            const int s = part == 0 ? i : R.n + i;
-            const int co = MS.path[2 * part][MS.plen[2 * part] - 1];
-            const int cn = MS.path[2 * part + 1][MS.plen[2 * part + 1] - 1];
-            const int lo = -1 - R.clink[co], ln = -1 - R.clink[cn];
-            const double4 nv = MS.contrib[2 * part + 1];
-            if (lo != ln) {
-                const int k = R.slot_of[s];
-                const int last = R.ccount[co] - 1;
-                const int bo = R.lbase[lo];
-                const int moved = R.pidx[bo + last];
-                R.pool4[bo + k] = R.pool4[bo + last];
-                R.pidx[bo + k] = moved;
-                if (moved >= 0 && moved < R.nsrc) R.slot_of[moved] = k;
+        // leaf states: cell, base, count of up to four leaves, followed through the moves
+        int lc[4], lb[4], ln[4];
+        int nl = 0;
+        auto find = [&](int cell, int base, int count) {
+            for (int k = 0; k < nl; ++k)
+                if (lc[k] == cell) return k;
+            lc[nl] = cell; lb[nl] = base; ln[nl] = count;
+            return nl++;
+        };
+        const int a = find(MS.tr[0].x, MS.lm_old[0].z, MS.lm_old[0].x);
+        const int b = find(MS.path[1][MS.plen[1] - 1], MS.lm_new[0].z, MS.lm_new[0].x);
+        int img_slot = imgs ? MS.tr[1].y : -1;
+        const int K = R.n + i;
+        const double4 ion_new = MS.contrib[1];
+        if (a != b) {
+            const int k = MS.tr[0].y, last = ln[a] - 1;
+            const int moved = MS.last_pidx[0];
+            if (k != last) {
+                R.pool4[lb[a] + k] = MS.last_pool[0];
+                R.pidx[lb[a] + k] = moved;
+                if (moved >= 0 && moved < R.nsrc) R.track[moved] = make_int2(lc[a], k);
                 else MS.err = kErrCommitSource;
-                R.ccount[co] = last;
-                const int cnt = R.ccount[cn], bn = R.lbase[ln];
-                R.pool4[bn + cnt] = nv;
-                R.pidx[bn + cnt] = s;
-                R.slot_of[s] = cnt;
-                R.leaf_of[s] = ln;
-                R.ccount[cn] = cnt + 1;
-            } else {
-                R.pool4[R.lbase[lo] + R.slot_of[s]] = nv;
+                if (moved == K) img_slot = k;
             }
-            R.src[s] = nv;
+            ln[a] = last;
+            R.cm[lc[a]].x = last;
+            const int pos = ln[b];
+            R.pool4[lb[b] + pos] = ion_new;
+            R.pidx[lb[b] + pos] = i;
+            R.track[i] = make_int2(lc[b], pos);
+            ln[b] = pos + 1;
+            R.cm[lc[b]].x = pos + 1;
+        } else {
+            R.pool4[lb[a] + MS.tr[0].y] = ion_new;
+        }
+        R.src[i] = ion_new;
+        if (imgs) {
+            const int c_old = MS.tr[1].x;
+            const int touched = (c_old == lc[a] || c_old == lc[b]);
+            const int cc = find(c_old, MS.lm_old[1].z, MS.lm_old[1].x);
+            const int dd = find(MS.path[3][MS.plen[3] - 1], MS.lm_new[1].z, MS.lm_new[1].x);
+            const double4 img_new = MS.contrib[3];
+            if (cc != dd) {
+                const int last = ln[cc] - 1;
+                int moved;
+                double4 mv;
+                if (!touched) {
+                    moved = MS.last_pidx[1];
+                    mv = MS.last_pool[1];
+                } else {  // the ion's move changed this leaf: read its last entry again
+                    moved = R.pidx[lb[cc] + last];
+                    mv = R.pool4[lb[cc] + last];
+                }
+                if (img_slot != last) {
+                    R.pool4[lb[cc] + img_slot] = mv;
+                    R.pidx[lb[cc] + img_slot] = moved;
+                    if (moved >= 0 && moved < R.nsrc) R.track[moved] = make_int2(lc[cc], img_slot);
+                    else MS.err = kErrCommitSource;
+                }
+                ln[cc] = last;
+                R.cm[lc[cc]].x = last;
+                const int pos = ln[dd];
+                R.pool4[lb[dd] + pos] = img_new;
+                R.pidx[lb[dd] + pos] = K;
+                R.track[K] = make_int2(lc[dd], pos);
+                ln[dd] = pos + 1;
+                R.cm[lc[dd]].x = pos + 1;
+            } else {
+                R.pool4[lb[cc] + img_slot] = img_new;
+            }
+            R.src[K] = img_new;
         }
     }
-    int maxlen = 0;
-    for (int j = 0; j < nps; ++j) maxlen = MS.plen[j] > maxlen ? MS.plen[j] : maxlen;
-    const int items = nps * maxlen * NTERM;
-    for (int it = tid; it < items; it += BLOCK) {
-        const int k = it % NTERM, rest = it / NTERM;
-        const int l = rest % maxlen, j = rest / maxlen;
-        if (l >= MS.plen[j]) continue;
-        const int c = MS.path[j][l];
-        if (c < 0 || c >= R.ncell) continue;  // descents only store checked cells
-        bool owner = true;
-        for (int jj = 0; jj < j; ++jj)
-            if (l < MS.plen[jj] && MS.path[jj][l] == c) owner = false;
-        if (!owner) continue;
-        const double4 g = R.cgeo[c];
-        double m = R.M[(size_t)c * MSTR + k];
-        int dc = 0;
-        for (int jj = j; jj < nps; ++jj) {
-            if (l >= MS.plen[jj] || MS.path[jj][l] != c) continue;
-            const double4 s = MS.contrib[jj];
-            const double v = mono(k, s.x - g.x, s.y - g.y, s.z - g.z);
-            if (jj & 1) { m = m + s.w * v; ++dc; } else { m = m - s.w * v; --dc; }
+    // moments and counts of the distinct path cells: all loads first, then stores
+    const int items = MS.nlist * NTERM;
+    constexpr int G = 4;
+    for (int base = tid; base < items; base += G * BLOCK) {
+        double mk[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int it = base + u * BLOCK;
+            if (it < items) {
+                const int li = it / NTERM, k = it % NTERM;
+                mk[u] = R.M[(size_t)MS.list_cell[li] * MSTR + k];
+            }
         }
-        R.M[(size_t)c * MSTR + k] = m;
-        if (k == 0 && l < MS.plen[j] - 1 && dc != 0) R.ccount[c] += dc;
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int it = base + u * BLOCK;
+            if (it >= items) continue;
+            const int li = it / NTERM, k = it % NTERM;
+            const int c = MS.list_cell[li], mask = MS.list_mask[li];
+            const double4 g = MS.list_geo[li];
+            double m = mk[u];
+            int dc = 0;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                if (!(mask & (1 << jj))) continue;
+                const double4 s = MS.contrib[jj];
+                const double v = mono(k, s.x - g.x, s.y - g.y, s.z - g.z);
+                if (jj & 1) { m = m + s.w * v; ++dc; } else { m = m - s.w * v; --dc; }
+            }
+            R.M[(size_t)c * MSTR + k] = m;
+            if (k == 0 && (mask & 16) && dc != 0) R.cm[c].x += dc;
+        }
     }
     __syncthreads();
 }
@@ -521,15 +773,16 @@ __device__ void commit(const Rep& R, McShared& MS, int i) {
 template <int BLOCK>
 __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double rx,
                             double ry, double rz, double alpha, int mode) {
+    static_assert(BLOCK >= 128, "the commit prefetch runs on the second wave");
     const int tid = threadIdx.x;
     MoveOut out{kInf, 0, 0, 0, 0};
-    const double4 si = R.src[i];
-    if (outside(R, rx, ry, rz)) { out.reason = 1; return out; }
     const bool imgs = R.images != 0;
     const int nps = imgs ? 4 : 2;
+    const double4 si = R.src[i];
+    const double4 mo = imgs ? R.src[R.n + i] : make_double4(0, 0, 0, 0);
+    if (outside(R, rx, ry, rz)) { out.reason = 1; return out; }
     if (tid == 0) {
         const double4 sn = make_double4(rx, ry, rz, si.w);
-        const double4 mo = imgs ? R.src[R.n + i] : make_double4(0, 0, 0, 0);
         const double4 mn = imgs ? kelvin(R, rx, ry, rz, si.w) : make_double4(0, 0, 0, 0);
         const uint64_t kio = morton_key(R, si.x, si.y, si.z);
         const uint64_t kmo = imgs ? morton_key(R, mo.x, mo.y, mo.z) : 0;
@@ -550,14 +803,16 @@ __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i
         MS.key[2] = kmo;
         MS.key[3] = imgs ? morton_key(R, mn.x, mn.y, mn.z) : 0;
         MS.contrib[0] = si; MS.contrib[1] = sn; MS.contrib[2] = mo; MS.contrib[3] = mn;
+        MS.err = 0;
+        MS.nlist = 0;
     }
     if (tid < 4) { MS.path[tid][0] = 0; MS.plen[tid] = 0; }
-    if (tid == 0) MS.err = 0;
+    if (tid == 64 || tid == 65) MS.pf_stage[tid - 64] = (tid == 65 && !imgs) ? 3 : 0;
     __syncthreads();
     // one step of a root path: descend by the key's digit, or stop at the leaf
     auto step = [&](int level) {
         const int c = MS.path[tid][level];
-        const int link = (c >= 0 && c < R.ncell) ? R.clink[c] : -1;
+        const int link = (c >= 0 && c < R.ncell) ? R.cm[c].y : -1;
         if (c < 0 || c >= R.ncell || (link >= 0 && link + 8 > R.ncell)) {
             MS.err = kErrPathCell;
             MS.plen[tid] = level + 1;
@@ -567,22 +822,48 @@ __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i
         } else {
             if (link >= 0) MS.err = kErrPathDepth;
             MS.plen[tid] = level + 1;
+            if (tid & 1) {  // a new position's leaf: its slot state for the commit
+                const int4 m = R.cm[c];
+                MS.lm_new[tid >> 1] = m;
+                if (m.y >= 0 || m.z < 0 || m.x < 0 || m.z + m.w > R.pool) MS.err = kErrCommitLeaf;
+            }
         }
     };
-    // the four root paths descend one level per traversal level
+    // the root paths descend, and the commit state is gathered, one level per traversal level
     auto hook = [&](int level) {
         if (tid < nps && MS.plen[tid] == 0 && level < kMaxLevels) step(level);
+        if (tid == 64 || tid == 65) prefetch_stage(R, MS, tid - 64, tid == 64 ? i : R.n + i);
     };
-    const int levels = traverse<2, BLOCK>(R, S, 2, hook);
+    const int levels = traverse<2, BLOCK>(R, S, 2, MS.cnt2, hook);
     if (S.err) { out.stop = S.err == kErrStack ? -7 : -8; out.detail = S.err; __syncthreads(); return out; }
-    // the traversal may stop above a path's leaf (a cell holding only the
-    // excluded sources, or the image's path): finish those descents
     if (tid < nps) {
         for (int level = levels; MS.plen[tid] == 0 && level < kMaxLevels; ++level) step(level);
         if (MS.plen[tid] == 0) { MS.err = kErrPathDepth; MS.plen[tid] = 1; MS.path[tid][0] = 0; }
     }
+    if (tid == 64 || tid == 65) {
+        const int s = tid == 64 ? i : R.n + i;
+        for (int k = 0; k < 3 && MS.pf_stage[tid - 64] < 3; ++k) prefetch_stage(R, MS, tid - 64, s);
+        if (MS.pf_stage[tid - 64] != 3) MS.err = kErrCommitSlot;
+    }
     __syncthreads();
     if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
+    // distinct cells of the root paths (any order: each cell's updates are applied by one thread set)
+    for (int it = tid; it < nps * kMaxLevels; it += BLOCK) {
+        const int j = it / kMaxLevels, l = it % kMaxLevels;
+        if (l >= MS.plen[j]) continue;
+        const int c = MS.path[j][l];
+        bool owner = true;
+        for (int jj = 0; jj < j; ++jj)
+            if (l < MS.plen[jj] && MS.path[jj][l] == c) owner = false;
+        if (!owner) continue;
+        int mask = l < MS.plen[j] - 1 ? 16 : 0;
+        for (int jj = j; jj < nps; ++jj)
+            if (l < MS.plen[jj] && MS.path[jj][l] == c) mask |= 1 << jj;
+        const int slot = atomicAdd(&MS.nlist, 1);
+        MS.list_cell[slot] = c;
+        MS.list_mask[slot] = mask;
+        MS.list_geo[slot] = R.cgeo[c];
+    }
     const double po = S.res[0], pn = S.res[1];
     if (S.overlap || S.coincide) { out.reason = 2; __syncthreads(); return out; }
     const double q = si.w, l = R.l_B;
@@ -599,34 +880,21 @@ __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i
     else if (mode == 2) acc = true;
     if (!acc) { __syncthreads(); return out; }
     if (tid == 0) {
-        // leaves of the four paths and every slot the commit will touch, checked
-        bool sane = true;
-        int leafc[4] = {0, 0, 0, 0}, leaf[4] = {0, 0, 0, 0};
-        for (int j = 0; j < nps; ++j) {
-            leafc[j] = MS.path[j][MS.plen[j] - 1];
-            const int link = R.clink[leafc[j]];
-            leaf[j] = -1 - link;
-            if (link >= 0 || leaf[j] >= R.nleaf) sane = false;
-        }
-        for (int part = 0; sane && part < nps / 2; ++part) {
-            const int s = part == 0 ? i : R.n + i;
-            if (s < 0 || s >= R.nsrc) { sane = false; break; }
-            const int lo = leaf[2 * part];
-            const int k = R.slot_of[s], cnt = R.ccount[leafc[2 * part]];
-            if (R.leaf_of[s] != lo || k < 0 || k >= cnt || cnt > R.lcap[lo] ||
-                R.lbase[lo] + cnt > R.pool || R.pidx[R.lbase[lo] + k] != s)
-                sane = false;
-        }
+        // the tracked leaves must be the leaves the old positions' keys lead to,
+        // and the tracked slots must hold the movers
+        bool sane = MS.tr[0].x == MS.path[0][MS.plen[0] - 1] && MS.self_pidx[0] == i;
+        if (imgs) sane = sane && MS.tr[1].x == MS.path[2][MS.plen[2] - 1] && MS.self_pidx[1] == R.n + i;
+        sane = sane && MS.last_pidx[0] >= 0 && MS.last_pidx[0] < R.nsrc;
         bool ok = sane;
         if (sane) {
-            const int lio = leaf[0], lin = leaf[1];
-            if (lin != lio && R.ccount[leafc[1]] + 1 > R.lcap[lin]) ok = false;
+            const int cio = MS.tr[0].x, cin = MS.path[1][MS.plen[1] - 1];
+            if (cin != cio && MS.lm_new[0].x + 1 > MS.lm_new[0].w) ok = false;
             if (imgs) {
-                const int lmo = leaf[2], lmn = leaf[3];
-                if (lmn != lmo) {
-                    int c = R.ccount[leafc[3]];
-                    if (lin != lio) { if (lmn == lin) c += 1; if (lmn == lio) c -= 1; }
-                    if (c + 1 > R.lcap[lmn]) ok = false;
+                const int cmo = MS.tr[1].x, cmn = MS.path[3][MS.plen[3] - 1];
+                if (cmn != cmo) {
+                    int c = MS.lm_new[1].x;
+                    if (cin != cio) { if (cmn == cin) c += 1; if (cmn == cio) c -= 1; }
+                    if (c + 1 > MS.lm_new[1].w) ok = false;
                 }
             }
         } else {
@@ -638,13 +906,13 @@ __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i
     if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
     if (!MS.ok) { out.stop = -6; __syncthreads(); return out; }
     commit<BLOCK>(R, MS, i);
+    if (MS.err) { out.stop = -8; out.detail = MS.err; }
     out.accepted = 1;
     return out;
 }
 
-
 // ------------------------------------------------------------ kernels
-constexpr int kMcBlock = 256;
+constexpr int kMcBlock = 512;
 constexpr int kEnergyBlock = 256;
 constexpr int kEnergyTargets = 4;
 
@@ -752,7 +1020,8 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
     }
     if (tid == 0) { S.ovl_t = -1; S.ovl_ex = -1; S.n_ovl = 0; S.err = 0; S.overlap = 0; S.coincide = 0; }
     __syncthreads();
-    traverse<NTG, kEnergyBlock>(Rs, S, nv, [](int) {});
+    __shared__ int cnt2[2];
+    traverse<NTG, kEnergyBlock>(Rs, S, nv, cnt2, [](int) {});
     if (tid < nv) {
         const int ion = t0 + tid;
         const double4 si = Rs.src[ion];
@@ -769,6 +1038,127 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
     }
 }
 
+// Gradient of the treecode energy, step 1 (targets in groups of
+// kEnergyTargets): for each ion t the potential phi_t and the field F_t of
+// its interaction lists give the target side,
+//   dE/dx_t += -1/2 l_B q_t F_t,   dE/dq_t += 1/2 l_B phi_t,
+// while each pair's source side is scattered (near pairs into G, far cells
+// into their adjoint coefficients L).  eterm gets each ion's energy term as
+// in k_energy.
+__global__ void __launch_bounds__(kEnergyBlock) k_grad(Rep* reps, int r, double* L, double4* G,
+                                                       double4* Gt, double* eterm) {
+    constexpr int NTG = kEnergyTargets;
+    __shared__ Trav<NTG, kEnergyBlock, 4> S;
+    __shared__ Rep Rs;
+    __shared__ int cnt2[2];
+    load_rep(Rs, reps + r);
+    __syncthreads();
+    const int t0 = blockIdx.x * NTG;
+    const int nv = min(NTG, Rs.n - t0);
+    const int tid = threadIdx.x;
+    const bool imgs = Rs.images != 0;
+    if (tid < nv) {
+        const int ion = t0 + tid;
+        const double4 si = Rs.src[ion];
+        const double4 mo = imgs ? Rs.src[Rs.n + ion] : make_double4(0, 0, 0, 0);
+        S.tx[tid] = si.x; S.ty[tid] = si.y; S.tz[tid] = si.z;
+        S.ex_i[tid] = ion; S.ex_k[tid] = imgs ? Rs.n + ion : -1;
+        S.kx_i[tid] = morton_key(Rs, si.x, si.y, si.z);
+        S.kx_k[tid] = imgs ? morton_key(Rs, mo.x, mo.y, mo.z) : 0;
+        S.es_i[tid] = si; S.es_k[tid] = mo;
+        S.front[0][tid] = pack(0, tid, kFlagIon | (imgs ? kFlagImg : 0u));
+    }
+    if (tid == 0) { S.ovl_t = -1; S.ovl_ex = -1; S.n_ovl = 0; S.err = 0; S.overlap = 0; S.coincide = 0; }
+    __syncthreads();
+    const GradOut go{L, G, 0.5 * Rs.l_B};
+    traverse<NTG, kEnergyBlock>(Rs, S, nv, cnt2, [](int) {}, &go);
+    if (tid < nv) {
+        const int ion = t0 + tid;
+        const double4 si = Rs.src[ion];
+        const bool bad = S.err != 0;
+        if (bad && tid == 0) reps[r].err_detail = S.err;
+        const double ph = bad ? __builtin_nan("") : S.res[4 * tid];
+        double e = 0.5 * si.w * ph;
+        if (Rs.geom == 1) {
+            const double r2 = si.x * si.x + si.y * si.y + si.z * si.z;
+            if (imgs) e += 0.5 * Rs.gamma * Rs.a * si.w * si.w / (r2 - Rs.a2);
+            if (Rs.Qc != 0.0) e += Rs.Qc * si.w / sqrt(r2);
+        }
+        eterm[ion] = e;
+        const double w = 0.5 * Rs.l_B * si.w;
+        Gt[ion] = make_double4(-w * S.res[4 * tid + 1], -w * S.res[4 * tid + 2], -w * S.res[4 * tid + 3],
+                               0.5 * Rs.l_B * ph);
+    }
+}
+
+// Step 2, one thread per source: the source side of every far cell holding
+// it, sum over its ancestors A of L_A^n (y - c_A)^n, differentiated in y
+// (times q) and in q.
+__global__ void __launch_bounds__(256) k_adj_down(const Rep* reps, int r, const double* L, double4* G) {
+    const Rep& R = reps[r];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= R.nsrc) return;
+    const double4 y = R.src[s];
+    int c = R.track[s].x;
+    double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int guard = 0; c >= 0 && guard < kMaxLevels; ++guard) {
+        if (c >= R.ncell) { v = __builtin_nan(""); break; }
+        const double4 g = R.cgeo[c];
+        double T[NTERM], D[NTERM];
+        poly_rec<0, true>(T, D, 0.0, 0.0, 0.0, 0.0, y.x - g.x, y.y - g.y, y.z - g.z,
+                          (const double*)__builtin_assume_aligned(L + (size_t)c * MSTR, 32), v, gx, gy, gz);
+        c = R.cparent[c];
+    }
+    double4 o = G[s];
+    o.x += y.w * gx; o.y += y.w * gy; o.z += y.w * gz; o.w += v;
+    G[s] = o;
+}
+
+// Step 3, one thread per ion: both roles of the ion, its image mapped back
+// by the chain rule through q_K = gamma a q / |r| and r_K = a^2 r / |r|^2,
+// and the exact self-image and central-charge terms.
+__global__ void __launch_bounds__(256) k_chain(const Rep* reps, int r, const double4* G, const double4* Gt,
+                                               double* dEdr, double* dEdq) {
+    const Rep& R = reps[r];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R.n) return;
+    const double4 si = R.src[i];
+    const double x = si.x, y = si.y, z = si.z, q = si.w;
+    const double4 a = Gt[i], b = G[i];
+    double gx = a.x + b.x, gy = a.y + b.y, gz = a.z + b.z, gq = a.w + b.w;
+    const double l = R.l_B;
+    const double r2 = x * x + y * y + z * z;
+    if (R.images) {
+        const double4 h = G[R.n + i];
+        const double rn = sqrt(r2);
+        const double ir2 = 1.0 / r2, ir4 = ir2 * ir2;
+        const double rh = x * h.x + y * h.y + z * h.z;
+        gx += R.a2 * (h.x * ir2 - 2.0 * x * rh * ir4);
+        gy += R.a2 * (h.y * ir2 - 2.0 * y * rh * ir4);
+        gz += R.a2 * (h.z * ir2 - 2.0 * z * rh * ir4);
+        const double c = -R.gamma * R.a * q / (r2 * rn);
+        gx += h.w * c * x; gy += h.w * c * y; gz += h.w * c * z;
+        gq += h.w * R.gamma * R.a / rn;
+        const double den = r2 - R.a2;
+        const double cs = -l * R.gamma * R.a * q * q / (den * den);
+        gx += cs * x; gy += cs * y; gz += cs * z;
+        gq += l * R.gamma * R.a * q / den;
+    }
+    if (R.geom == 1 && R.Qc != 0.0) {
+        const double rn = sqrt(r2);
+        const double ir3 = 1.0 / (r2 * rn);
+        gx += -l * R.Qc * q * x * ir3; gy += -l * R.Qc * q * y * ir3; gz += -l * R.Qc * q * z * ir3;
+        gq += l * R.Qc / rn;
+    }
+    dEdr[3 * (size_t)i] = gx; dEdr[3 * (size_t)i + 1] = gy; dEdr[3 * (size_t)i + 2] = gz;
+    dEdq[i] = gq;
+}
+
+__global__ void __launch_bounds__(256) k_zero(double* p, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        p[k] = 0.0;
+}
+
 void run_mc(hipStream_t s, Rep* reps, const McArgs& a, int grid) {
     hipLaunchKernelGGL(k_mc, dim3(grid), dim3(kMcBlock), 0, s, reps, a);
 }
@@ -779,8 +1169,20 @@ void run_energy(hipStream_t s, Rep* reps, int r, int n, double* phi, double* ete
     const int grid = (n + kEnergyTargets - 1) / kEnergyTargets;
     hipLaunchKernelGGL(k_energy, dim3(grid), dim3(kEnergyBlock), 0, s, reps, r, phi, eterm);
 }
+void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq, double* eterm) {
+    const size_t nl = (size_t)w.ncell * MSTR, ng = 4 * (size_t)w.nsrc;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(4096, (nl + 255) / 256)), dim3(256), 0, s, w.L, nl);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(4096, (ng + 255) / 256)), dim3(256), 0, s,
+                       (double*)w.G, ng);
+    hipLaunchKernelGGL(k_grad, dim3((w.n + kEnergyTargets - 1) / kEnergyTargets), dim3(kEnergyBlock), 0, s, reps,
+                       r, w.L, w.G, w.Gt, eterm);
+    hipLaunchKernelGGL(k_adj_down, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
+                       (const double*)w.L, w.G);
+    hipLaunchKernelGGL(k_chain, dim3((w.n + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
+                       (const double4*)w.G, (const double4*)w.Gt, dEdr, dEdq);
+}
 
-const EvalOps kOps = {run_mc, run_move, run_energy, nullptr, kMcBlock};
+const EvalOps kOps = {run_mc, run_move, run_energy, run_grad, kMcBlock};
 
 }  // namespace BHMC_NS
 

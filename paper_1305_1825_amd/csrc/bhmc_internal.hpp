@@ -44,12 +44,20 @@ void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_leaves(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nterms, int mstride);
 
+// Workspace of one gradient evaluation (device memory, library-owned).
+struct GradWork {
+    double* L;            // adjoint coefficients, ncell rows of mstride
+    double4* G;           // per source: dE/dx, dE/dy, dE/dz, dE/dq through its source role
+    double4* Gt;          // per ion: the same through its target role
+    int ncell, nsrc, n;
+};
+
 // ---- evaluation (bhmc_eval.hip, one translation unit per expansion order)
 struct EvalOps {
     void (*mc)(hipStream_t s, Rep* reps, const McArgs& a, int grid);
     void (*move)(hipStream_t s, Rep* reps, int r, MoveIO* io_dev);
     void (*energy)(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm);
-    void (*grad)(hipStream_t s, Rep* reps, int r, int n, double* work, double* dEdr, double* dEdq,
+    void (*grad)(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq,
                  double* eterm);
     int mc_block;
 };

@@ -167,3 +167,8 @@ def config_large_asym(r: int = 0, seed: int = 0, n: int = 199999):
     x, y, z, q = shell_system(q, 20.5, 200.0, 0.5, seed=seed, tag=6, replica=r)
     P = shell_params(20.0, -200.0, 20.5, 200.0, theta=0.5, p=8, leaf_cap=32, hard_core=0.5)
     return dict(name="asym_N%d_p8" % n, params=P, x=x, y=y, z=z, q=q, step=1.0)
+
+
+def sample_indices(n: int, k: int, tag: int = 5, seed: int = 0) -> np.ndarray:
+    """k distinct ion indices drawn uniformly (for checks on sampled outputs)."""
+    return np.sort(_rng(tag, 0, seed).choice(n, size=min(k, n), replace=False))
