@@ -124,6 +124,69 @@ def run_batched(R, sweeps, seed=0):
                 n_min=min(sizes), n_max=max(sizes), n_total=sum(sizes))
 
 
+def run_gradient(theta=0.5, calls=3):
+    """Energy plus exact gradient of the 1e5-ion shell system, inputs resident."""
+    import torch
+    from paper_1305_1825_amd import bhmc, workloads as W
+    c = W.config_gradient_100k(theta=theta)
+    x, y, z, q = (torch.as_tensor(c[k], dtype=torch.float64, device="cuda:0") for k in ("x", "y", "z", "q"))
+    t = bhmc.Tree(c["params"], x, y, z, q)
+    t.energy_grad()  # allocates the workspace
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(calls):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        E, g, gq = t.energy_grad()
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t.energy()
+    e1.record(stream)
+    e1.synchronize()
+    inf = t.info()
+    t.close()
+    return dict(workload="N=100000 ions + images, shell 10.5<r<120, theta=%.1f, p=6, leaf 16" % theta,
+                ms_per_gradient=float(np.median(ms)), ms_energy_only=e0.elapsed_time(e1),
+                ions_per_s=len(c["x"]) / (float(np.median(ms)) / 1000.0), E=E, ncell=inf["ncell"])
+
+
+def run_large(sweeps, grad_replicas):
+    """64 replicas of the 199,999-ion 2:1 electrolyte (p = 8, leaf 32): sweeps, then the
+    energy gradient of the first grad_replicas replicas."""
+    import torch
+    from paper_1305_1825_amd import bhmc, workloads as W
+    R = 64
+    reps = [W.config_large_asym(r=r) for r in range(R)]
+    sizes = [len(rp["x"]) for rp in reps]
+    cat = [torch.as_tensor(np.concatenate([rp[k] for rp in reps]), dtype=torch.float64, device="cuda:0")
+           for k in ("x", "y", "z", "q")]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = bhmc.Tree([rp["params"] for rp in reps], *cat, n_per_replica=sizes)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st = t.batch_sweep(seed=0, n_sweeps=sweeps, step=1.0, use_graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    moves = sum(s["moves"] for s in st)
+    t0 = time.perf_counter()
+    for r in range(grad_replicas):
+        t.energy_grad(replica=r)
+    torch.cuda.synchronize()
+    gwall = time.perf_counter() - t0
+    t.close()
+    return dict(workload="64 replicas x N=199999 (2:1, a=20, Q=-200, shell 20.5<r<200) + images, "
+                         "theta=0.5, p=8, leaf 32", replicas=R, sweeps=sweeps, moves=moves,
+                wall=wall, moves_per_s=moves / wall, build_s=build_s,
+                gradient_s_per_replica=gwall / max(grad_replicas, 1))
+
+
 def cpu_baseline(c, seconds=12.0):
     import oracle as O
     P = c["params"]
@@ -149,6 +212,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-sweeps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true")
+    ap.add_argument("--large-sweeps", type=int, default=0,
+                    help="also run the 64 x 199,999-ion replicas for this many sweeps")
+    ap.add_argument("--large-grad", type=int, default=4, help="replicas whose gradient the large leg times")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -198,6 +265,12 @@ def main():
         b = run_batched(256, args.batched_sweeps)
         b["ratio_vs_plain"] = b["moves_per_s"] / value
         out["batched"] = b
+    if not args.no_gradient:
+        print("bench: gradient N=1e5", file=sys.stderr, flush=True)
+        out["gradient"] = run_gradient()
+    if args.large_sweeps > 0:
+        print("bench: large replicas", file=sys.stderr, flush=True)
+        out["large"] = run_large(args.large_sweeps, args.large_grad)
     if not args.no_cpu:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(c)

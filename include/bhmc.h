@@ -194,7 +194,10 @@ bhmc_status bhmc_mc_run(bhmc_tree* tree, int32_t replica, uint64_t seed, uint64_
  * largest replica first).  Replica r's sweeps use move indices continuing
  * from its own move counter (0 after build), so replica r alone through
  * bhmc_mc_run with the same seed gives the same chain.  use_graph = 1 captures
- * one sweep in a hipGraph and replays it.  stats_host (nullable): R entries. */
+ * one sweep in a hipGraph and replays it.  Replicas that stop before a move
+ * that would overflow a leaf index array are rebuilt together after the sweep
+ * and finish it in one more persistent launch, so every sweep ends with every
+ * replica at the end of its sweep.  stats_host (nullable): R entries. */
 bhmc_status bhmc_batch_sweep(bhmc_tree* tree, uint64_t seed, int32_t n_sweeps, double step,
                              int32_t use_graph, bhmc_stats* stats_host);
 

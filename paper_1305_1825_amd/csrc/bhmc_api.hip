@@ -107,12 +107,15 @@ struct bhmc_tree {
     int* queue = nullptr;
     int* list_all = nullptr;         // replicas, largest first
     int* list_one = nullptr;         // scratch list of one replica
+    int* list_rest = nullptr;        // replicas a sweep left unfinished
+    std::vector<int> order;          // replicas, largest first (host copy of list_all)
     long long* sweep_add = nullptr;  // n_r per replica
     bhmc::MoveIO* io = nullptr;
     double* eterm = nullptr; int eterm_n = 0;
     char* gwork = nullptr; size_t gwork_bytes = 0;  // gradient workspace
     double* scalar = nullptr;
     int mc_grid = 1;
+    int mc_wide = 1;                 // one replica: the 512-thread Metropolis kernel
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t graph_stream = nullptr;  // capture needs a stream other than the null stream
@@ -329,7 +332,7 @@ static void destroy(bhmc_tree* t) {
     if (t->graph_stream) hipStreamDestroy(t->graph_stream);
     for (void* p : t->arena1) if (p) hipFree(p);
     for (void* p : t->arena2) if (p) hipFree(p);
-    hipFree(t->reps); hipFree(t->queue); hipFree(t->list_all); hipFree(t->list_one);
+    hipFree(t->reps); hipFree(t->queue); hipFree(t->list_all); hipFree(t->list_one); hipFree(t->list_rest);
     hipFree(t->sweep_add); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar); hipFree(t->gwork);
     if (t->host) hipHostFree(t->host);
     if (t->pin) hipHostFree(t->pin);
@@ -370,6 +373,7 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     if (hipMalloc(&t->queue, sizeof(int)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "queue"));
     if (hipMalloc(&t->list_all, sizeof(int) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "list"));
     if (hipMalloc(&t->list_one, sizeof(int)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "list"));
+    if (hipMalloc(&t->list_rest, sizeof(int) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "list"));
     if (hipMalloc(&t->sweep_add, sizeof(long long) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "sweep"));
     if (hipMalloc(&t->io, sizeof(bhmc::MoveIO)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "io"));
     if (hipMalloc(&t->scalar, sizeof(double) * 4) != hipSuccess) return bail(fail(BHMC_ENOMEM, "scalar"));
@@ -383,6 +387,7 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     std::vector<int> order(R);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_per[a] > n_per[b]; });
+    t->order = order;
     std::vector<long long> add(n_per, n_per + R);
     if ((st = h2d(t, t->list_all, order.data(), sizeof(int) * R)) ||
         (st = h2d(t, t->sweep_add, add.data(), sizeof(long long) * R)))
@@ -390,7 +395,10 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     int dev = 0, ncu = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    t->mc_grid = std::max(1, std::min(R, ncu > 0 ? ncu : 256));
+    // one replica: one wide workgroup; replicas: two 256-thread workgroups per CU.  A handle
+    // always runs the same kernel, so a replica's chain does not depend on how it is advanced.
+    t->mc_wide = R == 1 ? 1 : 0;
+    t->mc_grid = R == 1 ? 1 : std::max(1, std::min(R, 2 * (ncu > 0 ? ncu : 256)));
     *out = t;
     return BHMC_OK;
 }
@@ -563,7 +571,7 @@ static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArg
         bhmc_status st0 = h2d(t, t->list_one, &r, sizeof(int));
         if (st0) return st0;
         bhmc::launch_reset_queue(t->stream, t->queue);
-        t->ops->mc(t->stream, t->reps, a, 1);
+        t->ops->mc(t->stream, t->reps, a, 1, t->mc_wide);
         HIP_TRY(hipGetLastError());
         bhmc_status st = download(t);
         if (st) return st;
@@ -614,6 +622,49 @@ extern "C" bhmc_status bhmc_mc_run(bhmc_tree* t, int32_t replica, uint64_t seed,
     return BHMC_OK;
 }
 
+// Replicas that a sweep left unfinished stopped before a move that would
+// overflow a leaf index array.  All of them are rebuilt in one build launch and
+// the rest of their moves run in one persistent launch over just those
+// replicas (largest first), until every replica has finished the sweep.
+static bhmc_status finish_sweep(bhmc_tree* t, const bhmc::McArgs& base, std::vector<long long>& rebuilds,
+                                std::vector<long long>& last_stop) {
+    for (;;) {
+        bhmc_status st = download(t);
+        if (st) return st;
+        std::vector<int> stalled, rest;
+        for (int r : t->order) {
+            const Rep& h = t->host[r];
+            if (h.mc_status == -7) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its LDS capacity", r);
+            if (h.mc_status == -8)
+                return fail(BHMC_EINTERNAL, "replica %d: device index check %d failed at move %lld", r, h.err_detail,
+                            h.move_next);
+            if (h.mc_status == -6) {
+                // a fresh tree leaves two spare slots in every leaf, so the same
+                // move cannot overflow twice in a row
+                if (h.move_next == last_stop[r])
+                    return fail(BHMC_ECAPACITY, "replica %d: move %lld overflows a fresh tree", r, h.move_next);
+                last_stop[r] = h.move_next;
+                stalled.push_back(r);
+            }
+            if (h.mc_status == -6 || h.move_next < h.move_end) rest.push_back(r);
+        }
+        if (rest.empty()) return BHMC_OK;
+        if (!stalled.empty()) {
+            if ((st = build_list(t, stalled, nullptr, nullptr, nullptr, nullptr, {}))) return st;
+            for (int r : stalled) ++rebuilds[r];
+        }
+        for (int r : rest) t->host[r].mc_status = 0;
+        if ((st = upload(t))) return st;
+        if ((st = h2d(t, t->list_rest, rest.data(), sizeof(int) * rest.size()))) return st;
+        bhmc::McArgs a = base;
+        a.list = t->list_rest;
+        a.nlist = (int)rest.size();
+        bhmc::launch_reset_queue(t->stream, t->queue);
+        t->ops->mc(t->stream, t->reps, a, std::min((int)rest.size(), t->mc_grid), t->mc_wide);
+        HIP_TRY(hipGetLastError());
+    }
+}
+
 extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_sweeps, double step,
                                         int32_t use_graph, bhmc_stats* stats_host) {
     if (!t) return fail(BHMC_EINVAL, "null tree");
@@ -632,8 +683,9 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
     a.list = t->list_all;
     a.nlist = t->R;
     a.queue = t->queue;
+    std::vector<long long> rebuilds(t->R, 0), last_stop(t->R, -1);
+    hipStream_t gs = t->stream;
     if (use_graph) {
-        hipStream_t gs = t->stream;
         if (!gs) {
             if (!t->graph_stream) HIP_TRY(hipStreamCreateWithFlags(&t->graph_stream, hipStreamNonBlocking));
             gs = t->graph_stream;
@@ -644,31 +696,22 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
             if (t->graph) { hipGraphDestroy(t->graph); t->graph = nullptr; }
             HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
             bhmc::launch_sweep_prep(gs, t->reps, t->R, t->queue, t->sweep_add);
-            t->ops->mc(gs, t->reps, a, t->mc_grid);
+            t->ops->mc(gs, t->reps, a, t->mc_grid, t->mc_wide);
             HIP_TRY(hipStreamEndCapture(gs, &t->graph));
             HIP_TRY(hipGraphInstantiate(&t->gexec, t->graph, nullptr, nullptr, 0));
             t->graph_ok = true; t->graph_seed = seed; t->graph_step = step;
         }
-        for (int s = 0; s < n_sweeps; ++s) HIP_TRY(hipGraphLaunch(t->gexec, gs));
-        if (gs != t->stream) HIP_TRY(hipStreamSynchronize(gs));
-    } else {
-        for (int s = 0; s < n_sweeps; ++s) {
-            bhmc::launch_sweep_prep(t->stream, t->reps, t->R, t->queue, t->sweep_add);
-            t->ops->mc(t->stream, t->reps, a, t->mc_grid);
-        }
     }
-    HIP_TRY(hipGetLastError());
-    if ((st = download(t))) return st;
-    std::vector<long long> rebuilds(t->R, 0);
-    for (int r = 0; r < t->R; ++r) {
-        const Rep& h = t->host[r];
-        if (h.mc_status == -7) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its LDS capacity", r);
-        if (h.mc_status == -8)
-            return fail(BHMC_EINTERNAL, "replica %d: device index check %d failed at move %lld", r, h.err_detail, h.move_next);
-        if (h.mc_status == -6 || h.move_next < h.move_end) {
-            bhmc::McArgs b = a;
-            if ((st = run_replica_until_done(t, r, b, &rebuilds[r]))) return st;
+    for (int s = 0; s < n_sweeps; ++s) {
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(t->gexec, gs));
+            if (gs != t->stream) HIP_TRY(hipStreamSynchronize(gs));
+        } else {
+            bhmc::launch_sweep_prep(t->stream, t->reps, t->R, t->queue, t->sweep_add);
+            t->ops->mc(t->stream, t->reps, a, t->mc_grid, t->mc_wide);
         }
+        HIP_TRY(hipGetLastError());
+        if ((st = finish_sweep(t, a, rebuilds, last_stop))) return st;
     }
     if (stats_host) {
         for (int r = 0; r < t->R; ++r) {

@@ -655,7 +655,7 @@ __device__ __forceinline__ void prefetch_stage(const Rep& R, McShared& MS, int j
 // cells of the four root paths, applying to each cell, in order, the old ion
 // (-), the new ion (+), the old image (-) and the new image (+).
 template <int BLOCK>
-__device__ void commit(const Rep& R, McShared& MS, int i) {
+__device__ __forceinline__ void commit(const Rep& R, McShared& MS, int i) {
     const int tid = threadIdx.x;
     const bool imgs = R.images != 0;
     if (tid == 0) {
@@ -771,7 +771,7 @@ __device__ void commit(const Rep& R, McShared& MS, int i) {
 // mode 0: evaluate; 1: Metropolis with alpha, commit if accepted;
 // 2: commit unless rejected by a wall or an overlap.
 template <int BLOCK>
-__device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double rx,
+__device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double rx,
                             double ry, double rz, double alpha, int mode) {
     static_assert(BLOCK >= 128, "the commit prefetch runs on the second wave");
     const int tid = threadIdx.x;
@@ -912,7 +912,8 @@ __device__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i
 }
 
 // ------------------------------------------------------------ kernels
-constexpr int kMcBlock = 512;
+constexpr int kMcBlock = 512;      // a single chain: the widest traversal per move
+constexpr int kMcBlockBatch = 256; // replicas: two workgroups per CU hide each other's latency
 constexpr int kEnergyBlock = 256;
 constexpr int kEnergyTargets = 4;
 
@@ -929,8 +930,9 @@ __device__ __forceinline__ void load_rep(Rep& dst, const Rep* src) {
 // treecode energy change and the local adjustment of Sec. 3.3).  A replica
 // whose accepted move would overflow a leaf index array stops before that
 // move with mc_status = ECAPACITY; the host rebuilds it and resumes.
-__global__ void __launch_bounds__(kMcBlock) k_mc(Rep* reps, McArgs A) {
-    __shared__ Trav<2, kMcBlock> S;
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_mc(Rep* reps, McArgs A) {
+    __shared__ Trav<2, BLOCK> S;
     __shared__ McShared MS;
     __shared__ Rep Rs;
     __shared__ int s_r;
@@ -952,7 +954,7 @@ __global__ void __launch_bounds__(kMcBlock) k_mc(Rep* reps, McArgs A) {
         for (; m < mend; ++m) {
             const Draw d = draw_move(A.seed, (uint32_t)r, (uint64_t)m, Rs.n, A.step);
             const double4 si = Rs.src[d.i];
-            const MoveOut o = one_move<kMcBlock>(Rs, S, MS, d.i, si.x + d.dx, si.y + d.dy,
+            const MoveOut o = one_move<BLOCK>(Rs, S, MS, d.i, si.x + d.dx, si.y + d.dy,
                                                  si.z + d.dz, d.alpha, 1);
             if (o.stop) { status = o.stop; detail = o.detail; break; }
             ++st_moves;
@@ -1159,8 +1161,9 @@ __global__ void __launch_bounds__(256) k_zero(double* p, size_t n) {
         p[k] = 0.0;
 }
 
-void run_mc(hipStream_t s, Rep* reps, const McArgs& a, int grid) {
-    hipLaunchKernelGGL(k_mc, dim3(grid), dim3(kMcBlock), 0, s, reps, a);
+void run_mc(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide) {
+    if (wide) hipLaunchKernelGGL(k_mc<kMcBlock>, dim3(grid), dim3(kMcBlock), 0, s, reps, a);
+    else hipLaunchKernelGGL(k_mc<kMcBlockBatch>, dim3(grid), dim3(kMcBlockBatch), 0, s, reps, a);
 }
 void run_move(hipStream_t s, Rep* reps, int r, MoveIO* io) {
     hipLaunchKernelGGL(k_move, dim3(1), dim3(kMcBlock), 0, s, reps, r, io);
@@ -1182,7 +1185,7 @@ void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, 
                        (const double4*)w.G, (const double4*)w.Gt, dEdr, dEdq);
 }
 
-const EvalOps kOps = {run_mc, run_move, run_energy, run_grad, kMcBlock};
+const EvalOps kOps = {run_mc, run_move, run_energy, run_grad};
 
 }  // namespace BHMC_NS
 

@@ -54,12 +54,12 @@ struct GradWork {
 
 // ---- evaluation (bhmc_eval.hip, one translation unit per expansion order)
 struct EvalOps {
-    void (*mc)(hipStream_t s, Rep* reps, const McArgs& a, int grid);
+    // wide = 1: 512-thread workgroups (one chain); 0: 256-thread workgroups, two per CU (replicas)
+    void (*mc)(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide);
     void (*move)(hipStream_t s, Rep* reps, int r, MoveIO* io_dev);
     void (*energy)(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm);
     void (*grad)(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq,
                  double* eterm);
-    int mc_block;
 };
 const EvalOps* eval_ops(int p);
 

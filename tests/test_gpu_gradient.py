@@ -121,3 +121,36 @@ def test_autograd_function_backward():
     got = np.stack([xs[k].grad.cpu().numpy() for k in range(3)], axis=1)
     assert rel_err(got, 3.0 * dro) <= 1e-9
     assert rel_err(xs[3].grad.cpu().numpy(), 3.0 * dqo) <= 1e-9
+
+
+def test_gradient_matches_finite_differences_of_gpu_energy():
+    """Central differences (h = 1e-6) of the GPU treecode energy, each side a
+    fresh build; a displacement that crosses a MAC or cell boundary changes
+    the interaction list, so at most one component in the sample may differ."""
+    c = W.config_colloid_10k(n=600, p=6)
+    P = c["params"]
+    x, y, z, q = c["x"], c["y"], c["z"], c["q"]
+    _, g, gq = bhmc.Tree(P, x, y, z, q).energy_grad()
+    g = g.cpu().numpy()
+    gq = gq.cpu().numpy()
+    rms, rmsq = np.sqrt(np.mean(g ** 2)), np.sqrt(np.mean(gq ** 2))
+    h = 1e-6
+
+    def E(arrs):
+        return bhmc.Tree(P, *arrs).energy()
+
+    bad = 0
+    idx = W.sample_indices(len(x), 12, tag=5)
+    for i in idx:
+        for comp in range(4):
+            a1 = [a.copy() for a in (x, y, z, q)]
+            a2 = [a.copy() for a in (x, y, z, q)]
+            a1[comp][i] += h
+            a2[comp][i] -= h
+            fd = (E(a1) - E(a2)) / (2 * h)
+            ref = gq[i] if comp == 3 else g[i, comp]
+            scale = rmsq if comp == 3 else rms
+            if abs(fd - ref) > 1e-6 * (abs(ref) + scale):
+                say("  ion %d comp %d: fd %.9e grad %.9e" % (i, comp, fd, ref))
+                bad += 1
+    assert bad <= 1
