@@ -112,6 +112,7 @@ def run_batched(R, sweeps, seed=0):
     cat = [torch.as_tensor(np.concatenate([rp[k] for rp in reps]), dtype=torch.float64, device="cuda:0")
            for k in range(1, 5)]
     t = bhmc.Tree(Ps, *cat, n_per_replica=sizes)
+    tune = t.autotune(seed=seed, step=1.0, trial_moves=256)
     t.batch_sweep(seed=seed, n_sweeps=1, step=1.0, use_graph=True)  # warm-up sweep, builds the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -121,7 +122,7 @@ def run_batched(R, sweeps, seed=0):
     moves = sum(s["moves"] for s in st)
     t.close()
     return dict(moves=moves, wall=wall, moves_per_s=moves / wall, replicas=R, sweeps=sweeps,
-                n_min=min(sizes), n_max=max(sizes), n_total=sum(sizes))
+                n_min=min(sizes), n_max=max(sizes), n_total=sum(sizes), autotune=tune)
 
 
 def run_gradient(theta=0.5, calls=3):
@@ -170,6 +171,7 @@ def run_large(sweeps, grad_replicas):
     t = bhmc.Tree([rp["params"] for rp in reps], *cat, n_per_replica=sizes)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    tune = t.autotune(seed=0, step=1.0, trial_moves=128)
     t0 = time.perf_counter()
     st = t.batch_sweep(seed=0, n_sweeps=sweeps, step=1.0, use_graph=True)
     torch.cuda.synchronize()
@@ -183,7 +185,7 @@ def run_large(sweeps, grad_replicas):
     t.close()
     return dict(workload="64 replicas x N=199999 (2:1, a=20, Q=-200, shell 20.5<r<200) + images, "
                          "theta=0.5, p=8, leaf 32", replicas=R, sweeps=sweeps, moves=moves,
-                wall=wall, moves_per_s=moves / wall, build_s=build_s,
+                wall=wall, moves_per_s=moves / wall, build_s=build_s, autotune=tune,
                 gradient_s_per_replica=gwall / max(grad_replicas, 1))
 
 
@@ -216,6 +218,8 @@ def main():
     ap.add_argument("--large-sweeps", type=int, default=0,
                     help="also run the 64 x 199,999-ion replicas for this many sweeps")
     ap.add_argument("--large-grad", type=int, default=4, help="replicas whose gradient the large leg times")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="first copy a buffer of this size once (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -224,6 +228,14 @@ def main():
     import torch
     from paper_1305_1825_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: copied %d MiB (%d bytes read, %d written)" % (args.calibrate_copy, src.numel() * 8,
+                                                                    src.numel() * 8), file=sys.stderr, flush=True)
+        del src, dst
     c = W.config_colloid_10k()
     c["moves"] = args.moves
     print("bench: plain chain %s, %d moves/step, %d steps" % (c["name"], c["moves"], args.steps),

@@ -201,6 +201,20 @@ bhmc_status bhmc_mc_run(bhmc_tree* tree, int32_t replica, uint64_t seed, uint64_
 bhmc_status bhmc_batch_sweep(bhmc_tree* tree, uint64_t seed, int32_t n_sweeps, double step,
                              int32_t use_graph, bhmc_stats* stats_host);
 
+/* Autotuner of the replica kernel's launch shape.  Times trial_moves moves
+ * (at most N_r) of every replica with each candidate shape -- 0: 512-thread
+ * workgroups, one per CU; 1: 256-thread workgroups, one per CU; 2:
+ * 256-thread workgroups, two per CU -- rebuilding every replica from its
+ * built positions after each trial, and keeps the fastest for the handle's
+ * later bhmc_mc_run and bhmc_batch_sweep calls.  Needs the replicas as built
+ * (no moves run yet; EINVAL otherwise) and leaves them exactly as built.
+ * choice (nullable, host): the shape kept; ms_host (nullable, host, 3
+ * floats): each shape's trial time (0 if not tried: a one-replica handle
+ * tries shape 0 only).  The chain of a replica depends on the shape only
+ * through the rounding of its energy sums. */
+bhmc_status bhmc_batch_autotune(bhmc_tree* tree, uint64_t seed, double step, int32_t trial_moves,
+                                int32_t* choice, float* ms_host);
+
 /* Gradient of the treecode energy E of bhmc_energy for replica `replica`,
  * exact for the interaction lists its traversal makes (each far pair term
  * q_t q_j sum_n T_n(r_A - r_t) (r_j - r_A)^n of eq. 3.3 and each near pair

@@ -70,6 +70,7 @@ SIGNATURES = {
     "bhmc_commit_move": [_v, C.c_int64, _d],
     "bhmc_mc_run": [_v, C.c_int32, C.c_uint64, C.c_uint64, C.c_int64, C.c_double, _v, C.POINTER(Stats)],
     "bhmc_batch_sweep": [_v, C.c_uint64, C.c_int32, C.c_double, C.c_int32, C.POINTER(Stats)],
+    "bhmc_batch_autotune": [_v, C.c_uint64, C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)],
     "bhmc_energy_grad": [_v, C.c_int32, _v, _v, _d],
     "bhmc_get_state": [_v, C.c_int32, _v, _v, _v, _v],
     "bhmc_rebuild": [_v, C.c_int32],
@@ -221,6 +222,16 @@ class Tree:
         st = (Stats * R)()
         _check(lib().bhmc_batch_sweep(self.h, seed, n_sweeps, step, 1 if use_graph else 0, st), "batch_sweep")
         return [s.as_dict() for s in st]
+
+    SHAPES = ("512 threads, 1 per CU", "256 threads, 1 per CU", "256 threads, 2 per CU")
+
+    def autotune(self, seed=0, step=1.0, trial_moves=256):
+        """Pick the Metropolis kernel's launch shape by timing each on the replicas
+        as built; leaves them as built.  Returns the choice and each shape's ms."""
+        choice = C.c_int32()
+        ms = (C.c_float * len(self.SHAPES))()
+        _check(lib().bhmc_batch_autotune(self.h, seed, step, trial_moves, C.byref(choice), ms), "batch_autotune")
+        return dict(choice=int(choice.value), shape=self.SHAPES[choice.value], ms=[float(v) for v in ms])
 
     def energy_grad(self, replica=0):
         torch = _torch()

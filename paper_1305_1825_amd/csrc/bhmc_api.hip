@@ -513,7 +513,7 @@ extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* d
     w.L = (double*)t->gwork;
     w.G = (double4*)(t->gwork + lb);
     w.Gt = (double4*)(t->gwork + lb + gb);
-    w.ncell = h.ncell; w.nsrc = h.nsrc; w.n = n;
+    w.ncell = h.ncell; w.nleaf = h.nleaf; w.nsrc = h.nsrc; w.n = n;
     t->ops->grad(t->stream, t->reps, replica, w, dEdr_dev, dEdq_dev, t->eterm);
     HIP_TRY(hipGetLastError());
     return finish_energy(t, replica, n, E_host, "gradient");
@@ -721,6 +721,93 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
             s.rejected_overlap = g.stats[3]; s.rejected_metropolis = g.stats[4]; s.rebuilds = rebuilds[r];
         }
     }
+    return BHMC_OK;
+}
+
+// Launch shapes the replica autotuner tries: workgroup width (512 or 256
+// threads per traversal) and workgroups per CU (one, or two of 256 threads).
+struct LaunchShape { int wide, per_cu; };
+static const LaunchShape kShapes[] = {{1, 1}, {0, 1}, {0, 2}};
+
+extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double step, int32_t trial_moves,
+                                           int32_t* choice, float* ms_out) {
+    if (!t) return fail(BHMC_EINVAL, "null tree");
+    if (trial_moves < 1 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad trial_moves or step");
+    bhmc_status st = download(t);
+    if (st) return st;
+    for (int r = 0; r < t->R; ++r)
+        if (t->host[r].move_end != 0 || t->host[r].stats[0] != 0)
+            return fail(BHMC_EINVAL, "autotune needs replicas as built (replica %d has moved)", r);
+    int dev = 0, ncu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu <= 0) ncu = 256;
+    // the built positions, to rebuild every replica exactly as built after each trial
+    std::vector<long long> off(t->R);
+    long long ntot = 0;
+    for (int r = 0; r < t->R; ++r) { off[r] = ntot; ntot += t->host[r].n; }
+    double* saved = nullptr;
+    HIP_TRY(hipMalloc(&saved, sizeof(double) * 4 * (size_t)ntot));
+    struct Free { double* p; ~Free() { hipFree(p); } } guard{saved};
+    double *sx = saved, *sy = saved + ntot, *sz = saved + 2 * ntot, *sq = saved + 3 * ntot;
+    for (int r = 0; r < t->R; ++r) {
+        const Rep& h = t->host[r];
+        hipLaunchKernelGGL(bhmc::k_unpack, dim3(std::max(1, std::min(1024, (h.n + 255) / 256))), dim3(256), 0,
+                           t->stream, (const double4*)h.src, h.n, sx + off[r], sy + off[r], sz + off[r], sq + off[r]);
+    }
+    HIP_TRY(hipGetLastError());
+    std::vector<int> all(t->R);
+    std::iota(all.begin(), all.end(), 0);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 0.0f;
+    int best = -1;
+    const int nshape = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+    for (int k = 0; k < nshape && st == BHMC_OK; ++k) {
+        const LaunchShape sh = kShapes[k];
+        if (t->R == 1 && !sh.wide) continue;
+        for (int r = 0; r < t->R; ++r) {
+            Rep& h = t->host[r];
+            h.move_next = 0;
+            h.move_end = std::min<long long>(trial_moves, h.n);
+            h.mc_status = 0;
+        }
+        if ((st = upload(t))) break;
+        bhmc::McArgs a{};
+        a.seed = seed; a.step = step; a.list = t->list_all; a.nlist = t->R; a.queue = t->queue;
+        bhmc::launch_reset_queue(t->stream, t->queue);
+        const int grid = std::max(1, std::min(t->R, sh.per_cu * ncu));
+        if (hipEventRecord(e0, t->stream) != hipSuccess) { st = fail(BHMC_EHIP, "event"); break; }
+        t->ops->mc(t->stream, t->reps, a, grid, sh.wide);
+        if (hipEventRecord(e1, t->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(BHMC_EHIP, "trial launch failed");
+            break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms_out) ms_out[k] = ms;
+        if (best < 0 || ms < best_ms) { best = k; best_ms = ms; }
+        // back to the replicas as built
+        if ((st = download(t))) break;
+        if ((st = build_list(t, all, sx, sy, sz, sq, off))) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    if ((st = download(t))) return st;
+    for (int r = 0; r < t->R; ++r) {
+        Rep& h = t->host[r];
+        h.move_next = h.move_end = 0;
+        h.mc_status = 0;
+        h.err_detail = 0;
+        for (int q = 0; q < 6; ++q) h.stats[q] = 0;
+    }
+    if ((st = upload(t))) return st;
+    t->mc_wide = kShapes[best].wide;
+    t->mc_grid = std::max(1, std::min(t->R, kShapes[best].per_cu * ncu));
+    t->graph_ok = false;
+    if (choice) *choice = best;
     return BHMC_OK;
 }
 

@@ -132,50 +132,16 @@ __device__ __forceinline__ double far_eval(double Rx, double Ry, double Rz, cons
     return acc;
 }
 
-// ------------------------------------------------------------ far field, gradient form
-// One (target, far cell) pair of the exact gradient of the treecode energy.
-// With R = c - x and P(x) = sum_n T_n(R) M^n (eq. 3.3), the target side needs
-//   P   and   F_k = sum_m m_k T_m M^{m - e_k} = -dP/dx_k,
-// which takes T up to order p + 1.  The source side, sum_n T_n (y - c)^n per
-// member y, is carried by the cell's adjoint coefficients L^n += w T_n (n of
-// order <= p), added with device-wide atomics.
-template <int K>
-__device__ __forceinline__ void far_rec_grad(double (&T)[NTERM1], double Rx, double Ry, double Rz,
-                                             double ir2, const double* __restrict__ Mc,
-                                             double* __restrict__ Lc, double w, double& phi,
-                                             double& fx, double& fy, double& fz) {
-    if constexpr (K < NTERM1) {
-        constexpr TEnt e = TT1.e[K];
-        if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
-        if constexpr (K < NTERM) {
-            phi = fma(T[K], Mc[K], phi);
-            unsafeAtomicAdd(Lc + K, w * T[K]);
-        }
-        if constexpr (e.x1 >= 0) fx = fma((double)e.n1 * T[K], Mc[e.x1], fx);
-        if constexpr (e.y1 >= 0) fy = fma((double)e.n2 * T[K], Mc[e.y1], fy);
-        if constexpr (e.z1 >= 0) fz = fma((double)e.n3 * T[K], Mc[e.z1], fz);
-        far_rec_grad<K + 1>(T, Rx, Ry, Rz, ir2, Mc, Lc, w, phi, fx, fy, fz);
-    }
-}
-
 // Polynomial sum_n C_n d^n and its gradient sum_n C_n n_k d^{n - e_k} for
-// coefficients C that are either stored (STORED, in Cc) or T_n(R) computed
-// on the fly.  The monomials d^n are built by the same graded
+// stored coefficients C; the monomials d^n are built by the graded
 // recurrence, each from one of order |n| - 1.
-template <int K, bool STORED>
-__device__ __forceinline__ void poly_rec(double (&T)[NTERM], double (&D)[NTERM], double Rx, double Ry,
-                                         double Rz, double ir2, double dx, double dy, double dz,
-                                         const double* __restrict__ Cc, double& v, double& gx,
-                                         double& gy, double& gz) {
+template <int K>
+__device__ __forceinline__ void poly_rec(double (&D)[NTERM], double dx, double dy, double dz,
+                                         const double* __restrict__ Cc, double& v, double& gx, double& gy,
+                                         double& gz) {
     if constexpr (K < NTERM) {
         constexpr TEnt e = TT.e[K];
-        double c;
-        if constexpr (STORED) {
-            c = Cc[K];
-        } else {
-            if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
-            c = T[K];
-        }
+        const double c = Cc[K];
         if constexpr (K == 0) D[0] = 1.0;
         else if constexpr (e.n1 >= 1) D[K] = D[e.x1] * dx;
         else if constexpr (e.n2 >= 1) D[K] = D[e.y1] * dy;
@@ -184,17 +150,9 @@ __device__ __forceinline__ void poly_rec(double (&T)[NTERM], double (&D)[NTERM],
         if constexpr (e.x1 >= 0) gx = fma((double)e.n1 * c, D[e.x1], gx);
         if constexpr (e.y1 >= 0) gy = fma((double)e.n2 * c, D[e.y1], gy);
         if constexpr (e.z1 >= 0) gz = fma((double)e.n3 * c, D[e.z1], gz);
-        poly_rec<K + 1, STORED>(T, D, Rx, Ry, Rz, ir2, dx, dy, dz, Cc, v, gx, gy, gz);
+        poly_rec<K + 1>(D, dx, dy, dz, Cc, v, gx, gy, gz);
     }
 }
-
-// Where the per-source gradient goes: G[s] = (dE/dx, dE/dy, dE/dz, dE/dq) of
-// source s through its role as a source; L: adjoint coefficients per cell.
-struct GradOut {
-    double* L;
-    double4* G;
-    double half_lB;
-};
 
 // ------------------------------------------------------------ traversal state
 constexpr uint32_t kCellMask = 0xFFFFFFu;
@@ -209,7 +167,7 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-template <int NTG, int BLOCK, int NV = 1>
+template <int NTG, int BLOCK>
 struct Trav {
     static constexpr int FCAP = 4096;
     static constexpr int FARCAP = 1024 + BLOCK;
@@ -232,8 +190,8 @@ struct Trav {
     int err, overlap, coincide;
     uint64_t wcnt[2][NW];            // per-wave packed list counts, double buffered
     uint64_t wsum[NW + 1];
-    double red[NW][NTG * NV];
-    double res[NTG * NV];            // per target: potential, or (potential, F_x, F_y, F_z)
+    double red[NW][NTG];
+    double res[NTG];
 };
 
 template <int NTG>
@@ -243,21 +201,11 @@ __device__ __forceinline__ void add_to(double (&acc)[NTG], int t, double v) {
         if (k == t) acc[k] += v;
 }
 
-template <int NTG4>
-__device__ __forceinline__ void add_to4(double (&acc)[NTG4], int t, double v0, double v1, double v2,
-                                        double v3) {
-#pragma unroll
-    for (int k = 0; k < NTG4 / 4; ++k)
-        if (k == t) { acc[4 * k] += v0; acc[4 * k + 1] += v1; acc[4 * k + 2] += v2; acc[4 * k + 3] += v3; }
-}
-
 // Far cells, plus (index >= far_n) the cells holding an excluded source whose
-// corrected moments sit in LDS.  Gradient form (NV = 4): the target side is
-// accumulated per target, the source side goes to the cell's adjoint
-// coefficients.
-template <int NTG, int BLOCK, int NV>
-__device__ __forceinline__ void far_pass(const Rep& R, Trav<NTG, BLOCK, NV>& S, int far_n, int nflag,
-                                         double (&acc)[NTG * NV], const GradOut* go) {
+// corrected moments sit in LDS.
+template <int NTG, int BLOCK>
+__device__ __forceinline__ void far_pass(const Rep& R, Trav<NTG, BLOCK>& S, int far_n, int nflag,
+                                         double (&acc)[NTG]) {
     for (int j = threadIdx.x; j < far_n + nflag; j += BLOCK) {
         const bool fl = j >= far_n;
         const uint32_t e = fl ? S.flagl[j - far_n] : S.farl[j];
@@ -266,56 +214,13 @@ __device__ __forceinline__ void far_pass(const Rep& R, Trav<NTG, BLOCK, NV>& S, 
         const double4 g = R.cgeo[c];
         const double* Mc = fl ? S.Mx[j - far_n]
                               : (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32);
-        const double Rx = g.x - S.tx[t], Ry = g.y - S.ty[t], Rz = g.z - S.tz[t];
-        if constexpr (NV == 1) {
-            add_to<NTG>(acc, t, far_eval(Rx, Ry, Rz, Mc));
-        } else {
-            const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-            double T[NTERM1];
-            T[0] = rsqrt_nr(r2);
-            const double ir2 = T[0] * T[0];
-            const double w = go->half_lB * S.es_i[t].w;
-            double phi = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-            far_rec_grad<0>(T, Rx, Ry, Rz, ir2, Mc, go->L + (size_t)c * MSTR, w, phi, fx, fy, fz);
-            add_to4<NTG * NV>(acc, t, phi, fx, fy, fz);
-        }
-    }
-}
-
-// Gradient form: the adjoint coefficients of a flagged far cell also act on
-// the excluded sources inside it, which take no part in the target's
-// interactions; their pair terms w q_e sum_n T_n (y_e - c)^n are taken back
-// out of G here (one lane per (flagged cell, excluded source)).
-template <int NTG, int BLOCK, int NV>
-__device__ void flag_corrections(const Rep& R, Trav<NTG, BLOCK, NV>& S, int nflag, const GradOut* go) {
-    for (int j = threadIdx.x; j < 2 * nflag; j += BLOCK) {
-        const uint32_t e = S.flagl[j >> 1];
-        const int x = j & 1;
-        if (!(e & (x ? kFlagImg : kFlagIon))) continue;
-        const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
-        if (c >= R.ncell) { S.err = kErrFlagCell; continue; }
-        const double4 es = x ? S.es_k[t] : S.es_i[t];
-        const int sid = x ? S.ex_k[t] : S.ex_i[t];
-        if (sid < 0 || sid >= R.nsrc) { S.err = kErrFlagCell; continue; }
-        const double4 g = R.cgeo[c];
-        const double Rx = g.x - S.tx[t], Ry = g.y - S.ty[t], Rz = g.z - S.tz[t];
-        double T[NTERM], D[NTERM];
-        T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
-        const double ir2 = T[0] * T[0];
-        double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-        poly_rec<0, false>(T, D, Rx, Ry, Rz, ir2, es.x - g.x, es.y - g.y, es.z - g.z, nullptr, v, gx, gy, gz);
-        const double w = go->half_lB * S.es_i[t].w;
-        double4* G = go->G + sid;
-        unsafeAtomicAdd(&G->x, -w * es.w * gx);
-        unsafeAtomicAdd(&G->y, -w * es.w * gy);
-        unsafeAtomicAdd(&G->z, -w * es.w * gz);
-        unsafeAtomicAdd(&G->w, -w * v);
+        add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], Mc));
     }
 }
 
 // Exclusive scan of the near leaves' slot counts (in place in near_pre).
-template <int NTG, int BLOCK, int NV>
-__device__ int near_scan(Trav<NTG, BLOCK, NV>& S, int near_n) {
+template <int NTG, int BLOCK>
+__device__ int near_scan(Trav<NTG, BLOCK>& S, int near_n) {
     int carry = 0;
     for (int base = 0; base < near_n; base += BLOCK) {
         const int j = base + threadIdx.x;
@@ -331,10 +236,9 @@ __device__ int near_scan(Trav<NTG, BLOCK, NV>& S, int near_n) {
 
 // Near leaves: direct sum over each leaf's index array in slot order.  For
 // the overlap target, every ion other than the mover within tau is an overlap.
-// Gradient form: the pair term w q_j / |x - y_j| also goes to source j.
-template <int NTG, int BLOCK, int NV>
-__device__ __forceinline__ void near_pass(const Rep& R, Trav<NTG, BLOCK, NV>& S, int near_n, int total,
-                                          double (&acc)[NTG * NV], const GradOut* go) {
+template <int NTG, int BLOCK>
+__device__ __forceinline__ void near_pass(const Rep& R, Trav<NTG, BLOCK>& S, int near_n, int total,
+                                          double (&acc)[NTG]) {
     const int n_ion = R.n;
     for (int f = threadIdx.x; f < total; f += BLOCK) {
         int lo = 0, hi = near_n - 1;  // last j with near_pre[j] <= f
@@ -348,7 +252,7 @@ __device__ __forceinline__ void near_pass(const Rep& R, Trav<NTG, BLOCK, NV>& S,
         const double4 s = R.pool4[slot];
         const bool check_ovl = (t == S.ovl_t);
         int sid = -1;
-        if ((e & (kFlagIon | kFlagImg)) || check_ovl || NV > 1) {
+        if ((e & (kFlagIon | kFlagImg)) || check_ovl) {
             sid = R.pidx[slot];
             if (((e & kFlagIon) && sid == S.ex_i[t]) || ((e & kFlagImg) && sid == S.ex_k[t])) continue;
         }
@@ -356,20 +260,7 @@ __device__ __forceinline__ void near_pass(const Rep& R, Trav<NTG, BLOCK, NV>& S,
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (check_ovl && sid < n_ion && sid != S.ovl_ex && d2 <= R.tau2) S.overlap = 1;
         if (d2 == 0.0) { S.coincide = 1; continue; }
-        if constexpr (NV == 1) {
-            add_to<NTG>(acc, t, s.w * rsqrt_nr(d2));
-        } else {
-            if (sid < 0 || sid >= R.nsrc) { S.err = kErrNearSlots; continue; }
-            const double ir = rsqrt_nr(d2);
-            const double qi3 = s.w * (ir * ir * ir);
-            add_to4<NTG * NV>(acc, t, s.w * ir, qi3 * dx, qi3 * dy, qi3 * dz);
-            const double w = go->half_lB * S.es_i[t].w;
-            double4* G = go->G + sid;
-            unsafeAtomicAdd(&G->x, w * qi3 * dx);
-            unsafeAtomicAdd(&G->y, w * qi3 * dy);
-            unsafeAtomicAdd(&G->z, w * qi3 * dz);
-            unsafeAtomicAdd(&G->w, w * ir);
-        }
+        add_to<NTG>(acc, t, s.w * rsqrt_nr(d2));
     }
 }
 
@@ -382,9 +273,9 @@ __device__ __forceinline__ double box_dist2(double4 g, double x, double y, doubl
 
 // Hard-core check below cells the traversal took as far: descend every cell
 // whose cube comes within tau (plus a rounding margin) of the target.
-template <int NTG, int BLOCK, int NV>
-__device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK, NV>& S, int* cnt2) {
-    using TS = Trav<NTG, BLOCK, NV>;
+template <int NTG, int BLOCK>
+__device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK>& S, int* cnt2) {
+    using TS = Trav<NTG, BLOCK>;
     const int t = S.ovl_t;
     const double x = S.tx[t], y = S.ty[t], z = S.tz[t];
     const double reach = sqrt(R.tau2) + 1e-12 * R.side;
@@ -434,20 +325,17 @@ __device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK, NV>& S, int* cn
 // ballots and one barrier hand out list slots in a fixed order, so every sum
 // below is taken in the same order on every run.  On return S.res[t] holds
 // the potential at target t from every source except the target's excluded
-// ones (NV = 1), or S.res[4t .. 4t+3] holds that potential and the field F
-// of the far-field gradient form (NV = 4, which also sends each pair's
-// source side through go); S.err reports an overflowed list or a failed index check;
+// ones; S.err reports an overflowed list or a failed index check;
 // S.overlap / S.coincide report hard-core hits at the overlap target.
 // Returns the number of levels processed (hook is called once per level).
-template <int NTG, int BLOCK, int NV, class Hook>
-__device__ int traverse(const Rep& R, Trav<NTG, BLOCK, NV>& S, int nroot, int* cnt2, Hook&& hook,
-                        const GradOut* go = nullptr) {
-    using TS = Trav<NTG, BLOCK, NV>;
+template <int NTG, int BLOCK, class Hook>
+__device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2, Hook&& hook) {
+    using TS = Trav<NTG, BLOCK>;
     constexpr int NW = TS::NW;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    double acc[NTG * NV];
+    double acc[NTG];
 #pragma unroll
-    for (int k = 0; k < NTG * NV; ++k) acc[k] = 0.0;
+    for (int k = 0; k < NTG; ++k) acc[k] = 0.0;
     int cur = 0, fs = nroot, far_n = 0, near_n = 0, nflag = 0, buf = 0;
     bool failed = false;
     int level = 0;
@@ -457,14 +345,14 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK, NV>& S, int nroot, int* c
         for (int base = 0; base < fs; base += BLOCK) {
             if (far_n > TS::FARCAP - BLOCK) {
                 __syncthreads();
-                far_pass<NTG, BLOCK, NV>(R, S, far_n, 0, acc, go);
+                far_pass<NTG, BLOCK>(R, S, far_n, 0, acc);
                 far_n = 0;
                 __syncthreads();
             }
             if (near_n > TS::NEARCAP - BLOCK) {
                 __syncthreads();
-                const int total = near_scan<NTG, BLOCK, NV>(S, near_n);
-                near_pass<NTG, BLOCK, NV>(R, S, near_n, total, acc, go);
+                const int total = near_scan<NTG, BLOCK>(S, near_n);
+                near_pass<NTG, BLOCK>(R, S, near_n, total, acc);
                 near_n = 0;
                 __syncthreads();
             }
@@ -575,19 +463,18 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK, NV>& S, int nroot, int* c
         if (e & kFlagImg) { const double4 s = S.es_k[t]; mk = mk - s.w * mono(k, s.x - g.x, s.y - g.y, s.z - g.z); }
         S.Mx[f][k] = mk;
     }
-    const int total = near_scan<NTG, BLOCK, NV>(S, near_n);  // its barriers also publish Mx
-    far_pass<NTG, BLOCK, NV>(R, S, far_n, nflag, acc, go);
-    if constexpr (NV > 1) flag_corrections<NTG, BLOCK, NV>(R, S, nflag, go);
-    near_pass<NTG, BLOCK, NV>(R, S, near_n, total, acc, go);
+    const int total = near_scan<NTG, BLOCK>(S, near_n);  // its barriers also publish Mx
+    far_pass<NTG, BLOCK>(R, S, far_n, nflag, acc);
+    near_pass<NTG, BLOCK>(R, S, near_n, total, acc);
     __syncthreads();
-    if (S.ovl_t >= 0 && S.n_ovl > 0 && S.err == 0) overlap_below_far<NTG, BLOCK, NV>(R, S, cnt2);
+    if (S.ovl_t >= 0 && S.n_ovl > 0 && S.err == 0) overlap_below_far<NTG, BLOCK>(R, S, cnt2);
 #pragma unroll
-    for (int k = 0; k < NTG * NV; ++k) {
+    for (int k = 0; k < NTG; ++k) {
         const double sum = wave_sum(acc[k]);
         if (lane == 0) S.red[w][k] = sum;
     }
     __syncthreads();
-    if (tid < NTG * NV) {
+    if (tid < NTG) {
         double sum = 0.0;
         for (int ww = 0; ww < NW; ++ww) sum += S.red[ww][tid];
         S.res[tid] = sum;
@@ -1040,56 +927,376 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
     }
 }
 
-// Gradient of the treecode energy, step 1 (targets in groups of
-// kEnergyTargets): for each ion t the potential phi_t and the field F_t of
-// its interaction lists give the target side,
-//   dE/dx_t += -1/2 l_B q_t F_t,   dE/dq_t += 1/2 l_B phi_t,
-// while each pair's source side is scattered (near pairs into G, far cells
-// into their adjoint coefficients L).  eterm gets each ion's energy term as
-// in k_energy.
-__global__ void __launch_bounds__(kEnergyBlock) k_grad(Rep* reps, int r, double* L, double4* G,
-                                                       double4* Gt, double* eterm) {
-    constexpr int NTG = kEnergyTargets;
-    __shared__ Trav<NTG, kEnergyBlock, 4> S;
+// Gradient of the treecode energy, step 1.  One workgroup per leaf B takes the
+// ions of B, at most 16 at a time, as the targets of one shared traversal:
+// a frontier entry is a cell with three 16-bit masks (targets for which the
+// cell is still open, targets summing every source below it directly (the
+// N_0 rule), targets whose own image lies inside the cell) and a flag telling
+// whether the cell holds B.  Each target takes exactly the decisions its own
+// traversal would take (Sec. 3.2), so the interaction lists are the same.
+// Far cells and near leaves are then evaluated by 16-lane rows with lane k
+// serving target k: a row evaluates one far cell for all its targets, giving
+// each the potential P and the field F_k = sum_m m_k T_m M^{m - e_k} (T up
+// to order p + 1), and sums the targets' adjoint coefficients w T_n across the
+// row before one device atomic per term; a near leaf is walked source by
+// source, each pair's source side summed across the row before it is added
+// to G.  The far cell that holds a target's own image is corrected afterwards
+// (its pair terms with the image are taken out of P, F and G).  Per target:
+//   dE/dx_t += -1/2 l_B q_t F_t,   dE/dq_t += 1/2 l_B P_t,
+// and eterm gets the ion's energy term as in k_energy.
+constexpr int kGradBlock = 256;
+constexpr int kGradRows = kGradBlock / 16;
+constexpr int kGT = 16;
+
+struct GradShared {
+    static constexpr int FCAP = 2048;
+    static constexpr int FARCAP = 1024 + kGradBlock;
+    static constexpr int NEARCAP = 512 + kGradBlock;
+    static constexpr int NW = kGradBlock / 64;
+    uint32_t fc[2][FCAP];          // cell | (cell holds B) << 31
+    uint64_t fm[2][FCAP];          // open | direct << 16 | image inside << 32
+    uint32_t farc[FARCAP], farm[FARCAP];
+    uint32_t nearc[NEARCAP], nearm[NEARCAP];
+    double tx[kGT], ty[kGT], tz[kGT], tq[kGT];
+    int ion[kGT];
+    uint64_t kimg[kGT];
+    double4 img[kGT];
+    int flag_cell[kGT];
+    int nt, slot_next;
+    uint64_t kB;
+    int levB;
+    uint64_t wcnt[2][NW];
+    double red[kGradRows][kGT][4];
+    int err;
+};
+
+__device__ __forceinline__ double row_sum16(double v) {
+    v += __shfl_xor(v, 8, 16);
+    v += __shfl_xor(v, 4, 16);
+    v += __shfl_xor(v, 2, 16);
+    v += __shfl_xor(v, 1, 16);
+    return v;
+}
+
+// T up to order p + 1 for one (far cell, target) pair of a row: P and F for
+// the lane's target; the row's sum of w T_n goes to L, term K by lane K mod 16.
+template <int K>
+__device__ __forceinline__ void far_rec_row(double (&T)[NTERM1], double Rx, double Ry, double Rz, double ir2,
+                                            const double* __restrict__ Mc, double* __restrict__ Lc, double w,
+                                            int k, double& phi, double& fx, double& fy, double& fz) {
+    if constexpr (K < NTERM1) {
+        constexpr TEnt e = TT1.e[K];
+        if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
+        if constexpr (K < NTERM) {
+            phi = fma(T[K], Mc[K], phi);
+            const double v = row_sum16(w * T[K]);
+            if (k == (K & 15)) unsafeAtomicAdd(Lc + K, v);
+        }
+        if constexpr (e.x1 >= 0) fx = fma((double)e.n1 * T[K], Mc[e.x1], fx);
+        if constexpr (e.y1 >= 0) fy = fma((double)e.n2 * T[K], Mc[e.y1], fy);
+        if constexpr (e.z1 >= 0) fz = fma((double)e.n3 * T[K], Mc[e.z1], fz);
+        far_rec_row<K + 1>(T, Rx, Ry, Rz, ir2, Mc, Lc, w, k, phi, fx, fy, fz);
+    }
+}
+
+// Pair terms of a target with its own image y inside a far cell: with
+// D_n = (y - c)^n, v = sum_{|n|<=p} T_n D_n, F_k = sum_{|m|<=p+1} m_k T_m D_{m-e_k}
+// (the image's part of the target's field) and G_k = sum_{|n|<=p} n_k T_n D_{n-e_k}
+// (the image's own gradient of v).
+template <int K>
+__device__ __forceinline__ void flag_rec(double (&T)[NTERM1], double (&D)[NTERM], double Rx, double Ry, double Rz,
+                                         double ir2, double dx, double dy, double dz, double& v, double (&F)[3],
+                                         double (&G)[3]) {
+    if constexpr (K < NTERM1) {
+        constexpr TEnt e = TT1.e[K];
+        if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
+        if constexpr (K < NTERM) {
+            if constexpr (K == 0) D[0] = 1.0;
+            else if constexpr (e.n1 >= 1) D[K] = D[e.x1] * dx;
+            else if constexpr (e.n2 >= 1) D[K] = D[e.y1] * dy;
+            else D[K] = D[e.z1] * dz;
+            v = fma(T[K], D[K], v);
+            if constexpr (e.x1 >= 0) G[0] = fma((double)e.n1 * T[K], D[e.x1], G[0]);
+            if constexpr (e.y1 >= 0) G[1] = fma((double)e.n2 * T[K], D[e.y1], G[1]);
+            if constexpr (e.z1 >= 0) G[2] = fma((double)e.n3 * T[K], D[e.z1], G[2]);
+        }
+        if constexpr (e.x1 >= 0) F[0] = fma((double)e.n1 * T[K], D[e.x1], F[0]);
+        if constexpr (e.y1 >= 0) F[1] = fma((double)e.n2 * T[K], D[e.y1], F[1]);
+        if constexpr (e.z1 >= 0) F[2] = fma((double)e.n3 * T[K], D[e.z1], F[2]);
+        flag_rec<K + 1>(T, D, Rx, Ry, Rz, ir2, dx, dy, dz, v, F, G);
+    }
+}
+
+// Far list, then near list, of the group: rows of 16 lanes, lane k = target k.
+__device__ __forceinline__ void grad_rows(const Rep& R, GradShared& S, int far_n, int near_n, double* L, double4* G,
+                                          double half_lB, double (&acc)[4]) {
+    const int row = threadIdx.x >> 4, k = threadIdx.x & 15;
+    const int nt = S.nt;
+    const bool tk = k < nt;
+    const int kk = tk ? k : 0;
+    const double xk = S.tx[kk], yk = S.ty[kk], zk = S.tz[kk];
+    const double wk = half_lB * S.tq[kk];
+    for (int j = row; j < far_n; j += kGradRows) {
+        const int c = (int)S.farc[j];
+        if (c >= R.ncell) { S.err = kErrFarCell; continue; }
+        const bool act = tk && ((S.farm[j] >> k) & 1u);
+        const double4 g = R.cgeo[c];
+        const double Rx = g.x - xk, Ry = g.y - yk, Rz = g.z - zk;
+        double T[NTERM1];
+        T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
+        const double ir2 = T[0] * T[0];
+        double phi = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+        far_rec_row<0>(T, Rx, Ry, Rz, ir2, (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32),
+                       L + (size_t)c * MSTR, act ? wk : 0.0, k, phi, fx, fy, fz);
+        if (act) { acc[0] += phi; acc[1] += fx; acc[2] += fy; acc[3] += fz; }
+    }
+    const int n_ion = R.n;
+    const int own_img = R.images ? n_ion + S.ion[kk] : -1;
+    for (int j = row; j < near_n; j += kGradRows) {
+        const int c = (int)S.nearc[j];
+        if (c >= R.ncell) { S.err = kErrNearLeaf; continue; }
+        const int4 m = R.cm[c];
+        if (m.y >= 0 || m.x < 0 || m.z < 0 || m.z + m.x > R.pool) { S.err = kErrNearSlots; continue; }
+        const bool act = tk && ((S.nearm[j] >> k) & 1u);
+        for (int s = 0; s < m.x; ++s) {
+            const double4 src = R.pool4[m.z + s];
+            const int sid = R.pidx[m.z + s];
+            if (sid < 0 || sid >= R.nsrc) { S.err = kErrNearSlots; break; }
+            const double dx = xk - src.x, dy = yk - src.y, dz = zk - src.z;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            const bool use = act && sid != S.ion[kk] && sid != own_img && d2 != 0.0;
+            double sx = 0.0, sy = 0.0, sz = 0.0, sq = 0.0;
+            if (use) {
+                const double ir = rsqrt_nr(d2);
+                const double qi3 = src.w * (ir * ir * ir);
+                acc[0] += src.w * ir; acc[1] += qi3 * dx; acc[2] += qi3 * dy; acc[3] += qi3 * dz;
+                sx = wk * qi3 * dx; sy = wk * qi3 * dy; sz = wk * qi3 * dz; sq = wk * ir;
+            }
+            sx = row_sum16(sx); sy = row_sum16(sy); sz = row_sum16(sz); sq = row_sum16(sq);
+            double4* Gs = G + sid;
+            if (k == 0) unsafeAtomicAdd(&Gs->x, sx);
+            else if (k == 1) unsafeAtomicAdd(&Gs->y, sy);
+            else if (k == 2) unsafeAtomicAdd(&Gs->z, sz);
+            else if (k == 3) unsafeAtomicAdd(&Gs->w, sq);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, double* L, double4* G, double4* Gt,
+                                                     double* eterm) {
+    using GS = GradShared;
+    constexpr int NW = GS::NW;
+    __shared__ GS S;
     __shared__ Rep Rs;
-    __shared__ int cnt2[2];
     load_rep(Rs, reps + r);
     __syncthreads();
-    const int t0 = blockIdx.x * NTG;
-    const int nv = min(NTG, Rs.n - t0);
-    const int tid = threadIdx.x;
-    const bool imgs = Rs.images != 0;
-    if (tid < nv) {
-        const int ion = t0 + tid;
-        const double4 si = Rs.src[ion];
-        const double4 mo = imgs ? Rs.src[Rs.n + ion] : make_double4(0, 0, 0, 0);
-        S.tx[tid] = si.x; S.ty[tid] = si.y; S.tz[tid] = si.z;
-        S.ex_i[tid] = ion; S.ex_k[tid] = imgs ? Rs.n + ion : -1;
-        S.kx_i[tid] = morton_key(Rs, si.x, si.y, si.z);
-        S.kx_k[tid] = imgs ? morton_key(Rs, mo.x, mo.y, mo.z) : 0;
-        S.es_i[tid] = si; S.es_k[tid] = mo;
-        S.front[0][tid] = pack(0, tid, kFlagIon | (imgs ? kFlagImg : 0u));
+    const Rep& R = Rs;
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    const int leaf = blockIdx.x;
+    if (leaf >= R.nleaf) return;
+    const int B = R.lcell[leaf];
+    if (B < 0 || B >= R.ncell) {
+        if (tid == 0) reps[r].err_detail = kErrNearLeaf;
+        return;
     }
-    if (tid == 0) { S.ovl_t = -1; S.ovl_ex = -1; S.n_ovl = 0; S.err = 0; S.overlap = 0; S.coincide = 0; }
+    const int4 mB = R.cm[B];
+    if (mB.y >= 0 || mB.x < 0 || mB.z < 0 || mB.z + mB.x > R.pool) {
+        if (tid == 0) reps[r].err_detail = kErrNearSlots;
+        return;
+    }
+    const bool imgs = R.images != 0;
+    const double half_lB = 0.5 * R.l_B;
+    if (tid == 0) { S.slot_next = 0; S.kB = R.ckey[B]; S.levB = R.clevel[B]; }
     __syncthreads();
-    const GradOut go{L, G, 0.5 * Rs.l_B};
-    traverse<NTG, kEnergyBlock>(Rs, S, nv, cnt2, [](int) {}, &go);
-    if (tid < nv) {
-        const int ion = t0 + tid;
-        const double4 si = Rs.src[ion];
-        const bool bad = S.err != 0;
-        if (bad && tid == 0) reps[r].err_detail = S.err;
-        const double ph = bad ? __builtin_nan("") : S.res[4 * tid];
-        double e = 0.5 * si.w * ph;
-        if (Rs.geom == 1) {
-            const double r2 = si.x * si.x + si.y * si.y + si.z * si.z;
-            if (imgs) e += 0.5 * Rs.gamma * Rs.a * si.w * si.w / (r2 - Rs.a2);
-            if (Rs.Qc != 0.0) e += Rs.Qc * si.w / sqrt(r2);
+    for (;;) {
+        // the next (at most 16) ions of the leaf, in slot order
+        if (tid == 0) {
+            int s = S.slot_next, nt = 0;
+            for (; s < mB.x && nt < kGT; ++s) {
+                const int sid = R.pidx[mB.z + s];
+                if (sid >= 0 && sid < R.n) {
+                    const double4 p = R.pool4[mB.z + s];
+                    S.ion[nt] = sid;
+                    S.tx[nt] = p.x; S.ty[nt] = p.y; S.tz[nt] = p.z; S.tq[nt] = p.w;
+                    ++nt;
+                }
+            }
+            S.slot_next = s;
+            S.nt = nt;
+            S.err = 0;
         }
-        eterm[ion] = e;
-        const double w = 0.5 * Rs.l_B * si.w;
-        Gt[ion] = make_double4(-w * S.res[4 * tid + 1], -w * S.res[4 * tid + 2], -w * S.res[4 * tid + 3],
-                               0.5 * Rs.l_B * ph);
+        __syncthreads();
+        const int nt = S.nt;
+        if (nt == 0) break;
+        if (tid < nt) {
+            const double4 mo = imgs ? R.src[R.n + S.ion[tid]] : make_double4(0, 0, 0, 0);
+            S.img[tid] = mo;
+            S.kimg[tid] = imgs ? morton_key(R, mo.x, mo.y, mo.z) : 0;
+            S.flag_cell[tid] = -1;
+        }
+        if (tid == 0) {
+            const uint64_t all = (1ull << nt) - 1ull;
+            S.fc[0][0] = 0u | (1u << 31);
+            S.fm[0][0] = all | (imgs ? all << 32 : 0ull);
+        }
+        __syncthreads();
+        // ---- breadth-first traversal with target masks
+        int cur = 0, fs = 1, far_n = 0, near_n = 0, buf = 0;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        bool failed = false;
+        for (int level = 0; fs > 0 && !failed; ++level) {
+            int next_n = 0;
+            for (int base = 0; base < fs; base += kGradBlock) {
+                if (far_n > GS::FARCAP - kGradBlock || near_n > GS::NEARCAP - kGradBlock) {
+                    __syncthreads();
+                    grad_rows(R, S, far_n, near_n, L, G, half_lB, acc);
+                    far_n = 0; near_n = 0;
+                    __syncthreads();
+                }
+                const int j = base + tid;
+                const bool valid = j < fs;
+                const uint32_t ec = valid ? S.fc[cur][j] : 0u;
+                const uint64_t em = valid ? S.fm[cur][j] : 0ull;
+                const int c = (int)(ec & kCellMask);
+                const uint32_t anc = ec >> 31;
+                uint32_t farb = 0, nearb = 0, copen = 0, cdir = 0;
+                int4 m = make_int4(0, -1, 0, 0);
+                if (valid && c >= R.ncell) {
+                    S.err = kErrFrontCell;
+                } else if (valid) {
+                    m = R.cm[c];
+                    const double4 g = R.cgeo[c];
+                    if (m.y >= 0 && m.y + 8 > R.ncell) {
+                        S.err = kErrChildLink;
+                    } else {
+                        const uint32_t open = (uint32_t)(em & 0xFFFFu), dir = (uint32_t)((em >> 16) & 0xFFFFu);
+                        const uint32_t inimg = (uint32_t)((em >> 32) & 0xFFFFu);
+                        uint32_t todo = open | dir;
+                        while (todo) {
+                            const int t = __builtin_ctz(todo);
+                            todo &= todo - 1u;
+                            const uint32_t bit = 1u << t;
+                            const int np = m.x - (int)anc - (int)((inimg >> t) & 1u);
+                            if (np <= 0) continue;
+                            if (dir & bit) {
+                                if (m.y >= 0) cdir |= bit; else nearb |= bit;
+                                continue;
+                            }
+                            const double dx = g.x - S.tx[t], dy = g.y - S.ty[t], dz = g.z - S.tz[t];
+                            const double d2 = dx * dx + dy * dy + dz * dz;
+                            const bool mac = 3.0 * (g.w * g.w) <= R.theta2 * d2;
+                            if (mac && np >= R.n0) {
+                                farb |= bit;
+                                if (inimg & bit) S.flag_cell[t] = c;
+                            } else if (np > R.n0 && m.y >= 0) {
+                                copen |= bit;
+                            } else if (m.y < 0) {
+                                nearb |= bit;
+                            } else {
+                                cdir |= bit;
+                            }
+                        }
+                    }
+                }
+                const bool kf = farb != 0, kn = nearb != 0, ks = (copen | cdir) != 0;
+                const uint64_t lt = lanemask_lt();
+                const uint64_t bf = __ballot(kf), bn = __ballot(kn), bs = __ballot(ks);
+                if (lane == 0)
+                    S.wcnt[buf][w] = (uint64_t)__popcll(bf) | ((uint64_t)__popcll(bn) << 16) |
+                                     ((uint64_t)__popcll(bs) << 32);
+                __syncthreads();
+                uint64_t before = 0, tot = 0;
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) {
+                    const uint64_t v = S.wcnt[buf][ww];
+                    before += ww < w ? v : 0ull;
+                    tot += v;
+                }
+                buf ^= 1;
+                const int tf = (int)(tot & 0xffff), tn = (int)((tot >> 16) & 0xffff), ts = (int)((tot >> 32) & 0xffff);
+                if (next_n + 8 * ts > GS::FCAP) { failed = true; break; }  // uniform
+                if (kf) {
+                    const int o = far_n + (int)(before & 0xffff) + __popcll(bf & lt);
+                    S.farc[o] = (uint32_t)c;
+                    S.farm[o] = farb;
+                }
+                if (kn) {
+                    const int o = near_n + (int)((before >> 16) & 0xffff) + __popcll(bn & lt);
+                    S.nearc[o] = (uint32_t)c;
+                    S.nearm[o] = nearb;
+                }
+                if (ks) {
+                    const int o = next_n + 8 * ((int)((before >> 32) & 0xffff) + __popcll(bs & lt));
+                    const uint32_t live = copen | cdir;
+                    const uint32_t inimg = (uint32_t)((em >> 32) & 0xFFFFu) & live;
+                    const int dB = (anc && level + 1 <= S.levB) ? key_digit(S.kB, level + 1) : -1;
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        uint32_t im = 0;
+                        uint32_t rest = inimg;
+                        while (rest) {
+                            const int t = __builtin_ctz(rest);
+                            rest &= rest - 1u;
+                            if (key_digit(S.kimg[t], level + 1) == d) im |= 1u << t;
+                        }
+                        S.fc[cur ^ 1][o + d] = (uint32_t)(m.y + d) | (d == dB ? (1u << 31) : 0u);
+                        S.fm[cur ^ 1][o + d] = (uint64_t)copen | ((uint64_t)cdir << 16) | ((uint64_t)im << 32);
+                    }
+                }
+                far_n += tf; near_n += tn; next_n += 8 * ts;
+            }
+            __syncthreads();
+            cur ^= 1;
+            fs = next_n;
+        }
+        if (failed && tid == 0) S.err = kErrStack;
+        __syncthreads();
+        grad_rows(R, S, far_n, near_n, L, G, half_lB, acc);
+        // the far cell holding a target's own image: take the image's pair terms back out
+        if (tid < nt && S.flag_cell[tid] >= 0) {
+            const int c = S.flag_cell[tid];
+            const double4 g = R.cgeo[c];
+            const double4 y = S.img[tid];
+            const double Rx = g.x - S.tx[tid], Ry = g.y - S.ty[tid], Rz = g.z - S.tz[tid];
+            double T[NTERM1], D[NTERM];
+            T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
+            const double ir2 = T[0] * T[0];
+            double v = 0.0, F[3] = {0.0, 0.0, 0.0}, Gk[3] = {0.0, 0.0, 0.0};
+            flag_rec<0>(T, D, Rx, Ry, Rz, ir2, y.x - g.x, y.y - g.y, y.z - g.z, v, F, Gk);
+            acc[0] -= y.w * v; acc[1] -= y.w * F[0]; acc[2] -= y.w * F[1]; acc[3] -= y.w * F[2];
+            const double wt = half_lB * S.tq[tid];
+            double4* Gs = G + (R.n + S.ion[tid]);
+            unsafeAtomicAdd(&Gs->x, -wt * y.w * Gk[0]);
+            unsafeAtomicAdd(&Gs->y, -wt * y.w * Gk[1]);
+            unsafeAtomicAdd(&Gs->z, -wt * y.w * Gk[2]);
+            unsafeAtomicAdd(&Gs->w, -wt * v);
+        }
+        {
+            const int row = tid >> 4, k = tid & 15;
+            S.red[row][k][0] = acc[0]; S.red[row][k][1] = acc[1]; S.red[row][k][2] = acc[2]; S.red[row][k][3] = acc[3];
+        }
+        __syncthreads();
+        if (tid < nt) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            for (int rr = 0; rr < kGradRows; ++rr) {
+                a0 += S.red[rr][tid][0]; a1 += S.red[rr][tid][1]; a2 += S.red[rr][tid][2]; a3 += S.red[rr][tid][3];
+            }
+            const int ion = S.ion[tid];
+            const double q = S.tq[tid];
+            const bool bad = S.err != 0;
+            if (bad && tid == 0) reps[r].err_detail = S.err;
+            const double ph = bad ? __builtin_nan("") : a0;
+            double e = 0.5 * q * ph;
+            if (R.geom == 1) {
+                const double r2 = S.tx[tid] * S.tx[tid] + S.ty[tid] * S.ty[tid] + S.tz[tid] * S.tz[tid];
+                if (imgs) e += 0.5 * R.gamma * R.a * q * q / (r2 - R.a2);
+                if (R.Qc != 0.0) e += R.Qc * q / sqrt(r2);
+            }
+            eterm[ion] = e;
+            const double wq = half_lB * q;
+            Gt[ion] = make_double4(-wq * a1, -wq * a2, -wq * a3, half_lB * ph);
+        }
+        __syncthreads();
     }
 }
 
@@ -1106,9 +1313,9 @@ __global__ void __launch_bounds__(256) k_adj_down(const Rep* reps, int r, const 
     for (int guard = 0; c >= 0 && guard < kMaxLevels; ++guard) {
         if (c >= R.ncell) { v = __builtin_nan(""); break; }
         const double4 g = R.cgeo[c];
-        double T[NTERM], D[NTERM];
-        poly_rec<0, true>(T, D, 0.0, 0.0, 0.0, 0.0, y.x - g.x, y.y - g.y, y.z - g.z,
-                          (const double*)__builtin_assume_aligned(L + (size_t)c * MSTR, 32), v, gx, gy, gz);
+        double D[NTERM];
+        poly_rec<0>(D, y.x - g.x, y.y - g.y, y.z - g.z,
+                    (const double*)__builtin_assume_aligned(L + (size_t)c * MSTR, 32), v, gx, gy, gz);
         c = R.cparent[c];
     }
     double4 o = G[s];
@@ -1177,8 +1384,7 @@ void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, 
     hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(4096, (nl + 255) / 256)), dim3(256), 0, s, w.L, nl);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(4096, (ng + 255) / 256)), dim3(256), 0, s,
                        (double*)w.G, ng);
-    hipLaunchKernelGGL(k_grad, dim3((w.n + kEnergyTargets - 1) / kEnergyTargets), dim3(kEnergyBlock), 0, s, reps,
-                       r, w.L, w.G, w.Gt, eterm);
+    hipLaunchKernelGGL(k_grad, dim3(w.nleaf), dim3(kGradBlock), 0, s, reps, r, w.L, w.G, w.Gt, eterm);
     hipLaunchKernelGGL(k_adj_down, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
                        (const double*)w.L, w.G);
     hipLaunchKernelGGL(k_chain, dim3((w.n + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,

@@ -49,7 +49,7 @@ struct GradWork {
     double* L;            // adjoint coefficients, ncell rows of mstride
     double4* G;           // per source: dE/dx, dE/dy, dE/dz, dE/dq through its source role
     double4* Gt;          // per ion: the same through its target role
-    int ncell, nsrc, n;
+    int ncell, nleaf, nsrc, n;
 };
 
 // ---- evaluation (bhmc_eval.hip, one translation unit per expansion order)

@@ -274,13 +274,17 @@ def test_build_rejects_bad_input():
 
 
 # ---------------------------------------------------------------- batched replicas
-def test_batched_replicas_equal_single_chains():
+@pytest.mark.parametrize("tune", [False, True])
+def test_batched_replicas_equal_single_chains(tune):
     sizes = [int(v) for v in W.replica_sizes(6, seed=3, lo=200, hi=700)]
     reps = [W.batched_replica(r, n, seed=3) for r, n in enumerate(sizes)]
     Ps = [rp[0] for rp in reps]
     cat = [np.concatenate([rp[k] for rp in reps]) for k in range(1, 5)]
-    say("batched", sizes)
+    say("batched", sizes, "autotuned" if tune else "")
     g = bhmc.Tree(Ps, *cat, n_per_replica=sizes)
+    if tune:
+        # the trials must leave every replica exactly as built
+        say("  autotune", g.autotune(seed=5, step=1.0, trial_moves=100))
     stats = g.batch_sweep(seed=11, n_sweeps=2, step=1.0, use_graph=True)
     for r, (P, x, y, z, q) in enumerate(reps):
         o = O.Tree(P, x, y, z, q)
