@@ -227,7 +227,7 @@ bhmc_status bhmc_batch_autotune(bhmc_tree* tree, uint64_t seed, double step, int
  * values); E_host (nullable) receives E, bit-identical to bhmc_energy.  The
  * far-field source side is summed with device atomics, so the gradient can
  * differ between calls by rounding.  The library keeps a workspace of
- * 8 (ncell * round4(C(p+3,3)) + 4 nsrc + 4 n) bytes per handle. */
+ * about 8 (ncell * round4(C(p+3,3)) + 4.5 nsrc + 4.5 n) bytes per handle. */
 bhmc_status bhmc_energy_grad(bhmc_tree* tree, int32_t replica, double* dEdr_dev, double* dEdq_dev,
                              double* E_host);
 

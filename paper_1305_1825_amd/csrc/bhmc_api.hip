@@ -502,17 +502,22 @@ extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* d
     const size_t lb = align256(sizeof(double) * (size_t)h.ncell * t->mstride);
     const size_t gb = align256(sizeof(double) * 4 * (size_t)h.nsrc);
     const size_t tb = align256(sizeof(double) * 4 * (size_t)n);
-    if (t->gwork_bytes < lb + gb + tb) {
+    const size_t ob = align256(sizeof(int) * ((size_t)h.nsrc + 1));
+    const size_t ib = align256(sizeof(int) * (size_t)n);
+    const size_t need = lb + gb + tb + ob + ib;
+    if (t->gwork_bytes < need) {
         hipFree(t->gwork);
         t->gwork = nullptr;
         t->gwork_bytes = 0;
-        HIP_TRY(hipMalloc(&t->gwork, lb + gb + tb));
-        t->gwork_bytes = lb + gb + tb;
+        HIP_TRY(hipMalloc(&t->gwork, need));
+        t->gwork_bytes = need;
     }
     bhmc::GradWork w;
     w.L = (double*)t->gwork;
     w.G = (double4*)(t->gwork + lb);
     w.Gt = (double4*)(t->gwork + lb + gb);
+    w.rank = (int*)(t->gwork + lb + gb + tb);
+    w.islot = (int*)(t->gwork + lb + gb + tb + ob);
     w.ncell = h.ncell; w.nleaf = h.nleaf; w.nsrc = h.nsrc; w.n = n;
     t->ops->grad(t->stream, t->reps, replica, w, dEdr_dev, dEdq_dev, t->eterm);
     HIP_TRY(hipGetLastError());

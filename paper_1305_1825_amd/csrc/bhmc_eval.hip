@@ -927,13 +927,14 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
     }
 }
 
-// Gradient of the treecode energy, step 1.  One workgroup per leaf B takes the
-// ions of B, at most 16 at a time, as the targets of one shared traversal:
-// a frontier entry is a cell with three 16-bit masks (targets for which the
-// cell is still open, targets summing every source below it directly (the
-// N_0 rule), targets whose own image lies inside the cell) and a flag telling
-// whether the cell holds B.  Each target takes exactly the decisions its own
-// traversal would take (Sec. 3.2), so the interaction lists are the same.
+// Gradient of the treecode energy, step 1.  The ions, in the order of the
+// build's key sort, are cut into groups of 16; one workgroup
+// takes a group as the targets of one shared traversal: a frontier entry is a
+// cell with four 16-bit masks (targets for which the cell is still open,
+// targets summing every source below it directly (the N_0 rule), targets
+// whose own image lies inside the cell, targets whose own ion does).  Each
+// target takes exactly the decisions its own traversal would take (Sec. 3.2),
+// so the interaction lists are the same.
 // Far cells and near leaves are then evaluated by 16-lane rows with lane k
 // serving target k: a row evaluates one far cell for all its targets, giving
 // each the potential P and the field F_k = sum_m m_k T_m M^{m - e_k} (T up
@@ -949,22 +950,20 @@ constexpr int kGradRows = kGradBlock / 16;
 constexpr int kGT = 16;
 
 struct GradShared {
-    static constexpr int FCAP = 2048;
+    static constexpr int FCAP = 4096;
     static constexpr int FARCAP = 1024 + kGradBlock;
     static constexpr int NEARCAP = 512 + kGradBlock;
     static constexpr int NW = kGradBlock / 64;
-    uint32_t fc[2][FCAP];          // cell | (cell holds B) << 31
-    uint64_t fm[2][FCAP];          // open | direct << 16 | image inside << 32
+    uint32_t fc[2][FCAP];          // cell
+    uint64_t fm[2][FCAP];          // open | direct << 16 | image inside << 32 | ion inside << 48
     uint32_t farc[FARCAP], farm[FARCAP];
     uint32_t nearc[NEARCAP], nearm[NEARCAP];
     double tx[kGT], ty[kGT], tz[kGT], tq[kGT];
     int ion[kGT];
-    uint64_t kimg[kGT];
+    uint64_t kimg[kGT], kion[kGT];
     double4 img[kGT];
     int flag_cell[kGT];
-    int nt, slot_next;
-    uint64_t kB;
-    int levB;
+    int nt;
     uint64_t wcnt[2][NW];
     double red[kGradRows][kGT][4];
     int err;
@@ -1082,8 +1081,8 @@ __device__ __forceinline__ void grad_rows(const Rep& R, GradShared& S, int far_n
     }
 }
 
-__global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, double* L, double4* G, double4* Gt,
-                                                     double* eterm) {
+__global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int* islot, int nion, double* L,
+                                                     double4* G, double4* Gt, double* eterm) {
     using GS = GradShared;
     constexpr int NW = GS::NW;
     __shared__ GS S;
@@ -1092,52 +1091,37 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, double* L
     __syncthreads();
     const Rep& R = Rs;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    const int leaf = blockIdx.x;
-    if (leaf >= R.nleaf) return;
-    const int B = R.lcell[leaf];
-    if (B < 0 || B >= R.ncell) {
-        if (tid == 0) reps[r].err_detail = kErrNearLeaf;
-        return;
-    }
-    const int4 mB = R.cm[B];
-    if (mB.y >= 0 || mB.x < 0 || mB.z < 0 || mB.z + mB.x > R.pool) {
-        if (tid == 0) reps[r].err_detail = kErrNearSlots;
-        return;
-    }
+    const int g0 = blockIdx.x * kGT;
+    if (g0 >= nion) return;
     const bool imgs = R.images != 0;
     const double half_lB = 0.5 * R.l_B;
-    if (tid == 0) { S.slot_next = 0; S.kB = R.ckey[B]; S.levB = R.clevel[B]; }
-    __syncthreads();
-    for (;;) {
-        // the next (at most 16) ions of the leaf, in slot order
-        if (tid == 0) {
-            int s = S.slot_next, nt = 0;
-            for (; s < mB.x && nt < kGT; ++s) {
-                const int sid = R.pidx[mB.z + s];
-                if (sid >= 0 && sid < R.n) {
-                    const double4 p = R.pool4[mB.z + s];
-                    S.ion[nt] = sid;
-                    S.tx[nt] = p.x; S.ty[nt] = p.y; S.tz[nt] = p.z; S.tq[nt] = p.w;
-                    ++nt;
-                }
-            }
-            S.slot_next = s;
-            S.nt = nt;
-            S.err = 0;
-        }
+    {
+        if (tid == 0) { S.nt = min(kGT, nion - g0); S.err = 0; }
         __syncthreads();
         const int nt = S.nt;
-        if (nt == 0) break;
         if (tid < nt) {
-            const double4 mo = imgs ? R.src[R.n + S.ion[tid]] : make_double4(0, 0, 0, 0);
+            const int slot = islot[g0 + tid];
+            const int sid = (slot >= 0 && slot < R.pool) ? R.pidx[slot] : -1;
+            if (sid < 0 || sid >= R.n) {
+                S.err = kErrNearSlots;
+                S.ion[tid] = 0;
+                S.tx[tid] = 0.0; S.ty[tid] = 0.0; S.tz[tid] = 0.0; S.tq[tid] = 0.0;
+                S.kion[tid] = 0;
+            } else {
+                const double4 p = R.pool4[slot];
+                S.ion[tid] = sid;
+                S.tx[tid] = p.x; S.ty[tid] = p.y; S.tz[tid] = p.z; S.tq[tid] = p.w;
+                S.kion[tid] = morton_key(R, p.x, p.y, p.z);
+            }
+            const double4 mo = (imgs && sid >= 0 && sid < R.n) ? R.src[R.n + sid] : make_double4(0, 0, 0, 0);
             S.img[tid] = mo;
             S.kimg[tid] = imgs ? morton_key(R, mo.x, mo.y, mo.z) : 0;
             S.flag_cell[tid] = -1;
         }
         if (tid == 0) {
             const uint64_t all = (1ull << nt) - 1ull;
-            S.fc[0][0] = 0u | (1u << 31);
-            S.fm[0][0] = all | (imgs ? all << 32 : 0ull);
+            S.fc[0][0] = 0u;
+            S.fm[0][0] = all | (imgs ? all << 32 : 0ull) | (all << 48);
         }
         __syncthreads();
         // ---- breadth-first traversal with target masks
@@ -1158,7 +1142,6 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, double* L
                 const uint32_t ec = valid ? S.fc[cur][j] : 0u;
                 const uint64_t em = valid ? S.fm[cur][j] : 0ull;
                 const int c = (int)(ec & kCellMask);
-                const uint32_t anc = ec >> 31;
                 uint32_t farb = 0, nearb = 0, copen = 0, cdir = 0;
                 int4 m = make_int4(0, -1, 0, 0);
                 if (valid && c >= R.ncell) {
@@ -1171,12 +1154,13 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, double* L
                     } else {
                         const uint32_t open = (uint32_t)(em & 0xFFFFu), dir = (uint32_t)((em >> 16) & 0xFFFFu);
                         const uint32_t inimg = (uint32_t)((em >> 32) & 0xFFFFu);
+                        const uint32_t inion = (uint32_t)(em >> 48);
                         uint32_t todo = open | dir;
                         while (todo) {
                             const int t = __builtin_ctz(todo);
                             todo &= todo - 1u;
                             const uint32_t bit = 1u << t;
-                            const int np = m.x - (int)anc - (int)((inimg >> t) & 1u);
+                            const int np = m.x - (int)((inion >> t) & 1u) - (int)((inimg >> t) & 1u);
                             if (np <= 0) continue;
                             if (dir & bit) {
                                 if (m.y >= 0) cdir |= bit; else nearb |= bit;
@@ -1229,18 +1213,31 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, double* L
                     const int o = next_n + 8 * ((int)((before >> 32) & 0xffff) + __popcll(bs & lt));
                     const uint32_t live = copen | cdir;
                     const uint32_t inimg = (uint32_t)((em >> 32) & 0xFFFFu) & live;
-                    const int dB = (anc && level + 1 <= S.levB) ? key_digit(S.kB, level + 1) : -1;
+                    const uint32_t inion = (uint32_t)(em >> 48) & live;
+                    // the child digit of every live target's image and ion
+                    uint64_t dimg = 0, dion = 0;
+                    for (uint32_t rest = inimg; rest; rest &= rest - 1u) {
+                        const int t = __builtin_ctz(rest);
+                        dimg |= (uint64_t)key_digit(S.kimg[t], level + 1) << (4 * t);
+                    }
+                    for (uint32_t rest = inion; rest; rest &= rest - 1u) {
+                        const int t = __builtin_ctz(rest);
+                        dion |= (uint64_t)key_digit(S.kion[t], level + 1) << (4 * t);
+                    }
 #pragma unroll
                     for (int d = 0; d < 8; ++d) {
-                        uint32_t im = 0;
-                        uint32_t rest = inimg;
-                        while (rest) {
+                        uint32_t im = 0, io = 0;
+                        for (uint32_t rest = inimg; rest; rest &= rest - 1u) {
                             const int t = __builtin_ctz(rest);
-                            rest &= rest - 1u;
-                            if (key_digit(S.kimg[t], level + 1) == d) im |= 1u << t;
+                            if ((int)((dimg >> (4 * t)) & 15u) == d) im |= 1u << t;
                         }
-                        S.fc[cur ^ 1][o + d] = (uint32_t)(m.y + d) | (d == dB ? (1u << 31) : 0u);
-                        S.fm[cur ^ 1][o + d] = (uint64_t)copen | ((uint64_t)cdir << 16) | ((uint64_t)im << 32);
+                        for (uint32_t rest = inion; rest; rest &= rest - 1u) {
+                            const int t = __builtin_ctz(rest);
+                            if ((int)((dion >> (4 * t)) & 15u) == d) io |= 1u << t;
+                        }
+                        S.fc[cur ^ 1][o + d] = (uint32_t)(m.y + d);
+                        S.fm[cur ^ 1][o + d] = (uint64_t)copen | ((uint64_t)cdir << 16) | ((uint64_t)im << 32) |
+                                               ((uint64_t)io << 48);
                     }
                 }
                 far_n += tf; near_n += tn; next_n += 8 * ts;
@@ -1298,6 +1295,48 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, double* L
         }
         __syncthreads();
     }
+}
+
+// Ion groups of the gradient traversal: the ions in the order of the build's
+// key sort (a space-filling curve, so consecutive ions are close in space).
+// rank[k] counts the ions before sorted position k; islot[rank] is the
+// current slot of that ion.
+__global__ void __launch_bounds__(256) k_gcount(const Rep* reps, int r, int* rank) {
+    const Rep& R = reps[r];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < R.nsrc) rank[k] = (unsigned)R.perm[k] < (unsigned)R.n ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(1024) k_gscan(int* v, int nv) {
+    __shared__ uint64_t wsum[1024 / 64 + 1];
+    int carry = 0;
+    for (int base = 0; base < nv; base += 1024) {
+        const int j = base + threadIdx.x;
+        const int x = j < nv ? v[j] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_exscan<1024>((uint64_t)x, wsum, tot);
+        if (j < nv) v[j] = carry + (int)ex;
+        carry += (int)tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) v[nv] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_gfill(const Rep* reps, int r, const int* rank, int* islot) {
+    const Rep& R = reps[r];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= R.nsrc) return;
+    const int i = R.perm[k];
+    if ((unsigned)i >= (unsigned)R.n) return;
+    const int rk = rank[k];
+    if (rk < 0 || rk >= R.n) return;
+    const int2 tr = R.track[i];
+    int slot = -1;
+    if (tr.x >= 0 && tr.x < R.ncell) {
+        const int4 m = R.cm[tr.x];
+        if (m.y < 0 && tr.y >= 0 && tr.y < m.x && m.z >= 0 && m.z + m.x <= R.pool) slot = m.z + tr.y;
+    }
+    islot[rk] = slot;
 }
 
 // Step 2, one thread per source: the source side of every far cell holding
@@ -1384,7 +1423,13 @@ void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, 
     hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(4096, (nl + 255) / 256)), dim3(256), 0, s, w.L, nl);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(4096, (ng + 255) / 256)), dim3(256), 0, s,
                        (double*)w.G, ng);
-    hipLaunchKernelGGL(k_grad, dim3(w.nleaf), dim3(kGradBlock), 0, s, reps, r, w.L, w.G, w.Gt, eterm);
+    // ion groups: ranks of the ions in key order, then their slots
+    hipLaunchKernelGGL(k_gcount, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r, w.rank);
+    hipLaunchKernelGGL(k_gscan, dim3(1), dim3(1024), 0, s, w.rank, w.nsrc);
+    hipLaunchKernelGGL(k_gfill, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
+                       (const int*)w.rank, w.islot);
+    hipLaunchKernelGGL(k_grad, dim3((w.n + kGT - 1) / kGT), dim3(kGradBlock), 0, s, reps, r, (const int*)w.islot, w.n,
+                       w.L, w.G, w.Gt, eterm);
     hipLaunchKernelGGL(k_adj_down, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
                        (const double*)w.L, w.G);
     hipLaunchKernelGGL(k_chain, dim3((w.n + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,

@@ -49,6 +49,8 @@ struct GradWork {
     double* L;            // adjoint coefficients, ncell rows of mstride
     double4* G;           // per source: dE/dx, dE/dy, dE/dz, dE/dq through its source role
     double4* Gt;          // per ion: the same through its target role
+    int* rank;            // per sorted source: ions before it (nsrc + 1)
+    int* islot;           // per ion rank: its current slot (n)
     int ncell, nleaf, nsrc, n;
 };
 
