@@ -317,7 +317,11 @@ static bhmc_status build_list(bhmc_tree* t, const std::vector<int>& list, const 
     if ((st = upload(t))) return st;
     bhmc::launch_topology(t->stream, nr, t->reps, dlist);
     bhmc::launch_leaves(t->stream, nr, t->reps, dlist);
-    bhmc::launch_moments(t->stream, nr, t->reps, dlist, t->nterms, t->mstride);
+    HIP_TRY(hipGetLastError());
+    if ((st = download(t))) return st;  // cells per level size the moment launches
+    for (int r : list)
+        if (t->host[r].status) return fail(BHMC_EHIP, "replica %d: %s", r, status_name(t->host[r].status));
+    bhmc::launch_moments(t->stream, nr, t->reps, dlist, t->nterms, t->mstride, t->host, list.data());
     HIP_TRY(hipGetLastError());
     if ((st = download(t))) return st;
     for (int r : list)

@@ -10,6 +10,8 @@
 #include "bhmc_dev.hpp"
 #include "bhmc_internal.hpp"
 
+#include <algorithm>
+
 namespace bhmc {
 
 constexpr int kBuildBlock = 1024;
@@ -322,12 +324,17 @@ __device__ __forceinline__ int mindex_dev(int n1, int n2, int n3) {
 }
 
 // P2M at leaves: one thread per (leaf, term); d^n by repeated multiplication.
-__global__ void __launch_bounds__(kBuildBlock)
+// Moments are spread over many workgroups per replica: blockIdx.y picks the
+// replica, blockIdx.x a chunk of (cell, term) items.
+constexpr int kMomBlock = 256;
+
+__global__ void __launch_bounds__(kMomBlock)
 k_p2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
-    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
+    Rep& R = reps[rep_list ? rep_list[blockIdx.y] : blockIdx.y];
     if (R.status) return;  // a failed build leaves the leaf tables unusable
     const long long items = (long long)R.nleaf * nterms;
-    for (long long it = threadIdx.x; it < items; it += blockDim.x) {
+    for (long long it = blockIdx.x * (long long)kMomBlock + threadIdx.x; it < items;
+         it += (long long)gridDim.x * kMomBlock) {
         const int l = (int)(it / nterms), k = (int)(it % nterms);
         const int c = R.lcell[l];
         if (c < 0 || c >= R.ncell) continue;
@@ -349,44 +356,42 @@ k_p2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
     }
 }
 
-// M2M, deepest level first: with s = c_child - c_parent (every component
-// +-h_child, exact),
+// M2M of one level (the launches go deepest level first): with
+// s = c_child - c_parent (every component +-h_child, exact),
 //   M_parent^n = sum_children sum_{k <= n} C(n, k) s^(n-k) M_child^k.
-__global__ void __launch_bounds__(kBuildBlock)
-k_m2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
-    Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
-    if (R.status) return;
-    for (int level = R.depth - 1; level >= 0; --level) {
-        const int ls = R.level_start[level], le = R.level_start[level + 1];
-        const long long items = (long long)(le - ls) * nterms;
-        for (long long it = threadIdx.x; it < items; it += blockDim.x) {
-            const int c = ls + (int)(it / nterms), k = (int)(it % nterms);
-            const int first = R.cm[c].y;
-            if (first < 0 || first + 8 > R.ncell) continue;
-            const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
-            const double hc = R.cgeo[c].w * 0.5;
-            double acc = 0.0;
-            for (int d = 0; d < 8; ++d) {
-                const double sx = (d & 4) ? hc : -hc, sy = (d & 2) ? hc : -hc, sz = (d & 1) ? hc : -hc;
-                const double* Mc = R.M + (size_t)(first + d) * mstride;
-                double px = 1.0;
-                for (int k1 = n1; k1 >= 0; --k1) {      // s_x^(n1-k1) grows as k1 falls
-                    double py = 1.0;
-                    for (int k2 = n2; k2 >= 0; --k2) {
-                        double pz = 1.0;
-                        for (int k3 = n3; k3 >= 0; --k3) {
-                            const double coef = (double)(c_binom[n1][k1] * c_binom[n2][k2] * c_binom[n3][k3]);
-                            acc += coef * (px * py * pz) * Mc[mindex_dev(k1, k2, k3)];
-                            pz *= sz;
-                        }
-                        py *= sy;
+__global__ void __launch_bounds__(kMomBlock)
+k_m2m(Rep* reps, const int* rep_list, int nterms, int mstride, int level) {
+    Rep& R = reps[rep_list ? rep_list[blockIdx.y] : blockIdx.y];
+    if (R.status || level >= R.depth) return;
+    const int ls = R.level_start[level], le = R.level_start[level + 1];
+    const long long items = (long long)(le - ls) * nterms;
+    for (long long it = blockIdx.x * (long long)kMomBlock + threadIdx.x; it < items;
+         it += (long long)gridDim.x * kMomBlock) {
+        const int c = ls + (int)(it / nterms), k = (int)(it % nterms);
+        const int first = R.cm[c].y;
+        if (first < 0 || first + 8 > R.ncell) continue;
+        const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
+        const double hc = R.cgeo[c].w * 0.5;
+        double acc = 0.0;
+        for (int d = 0; d < 8; ++d) {
+            const double sx = (d & 4) ? hc : -hc, sy = (d & 2) ? hc : -hc, sz = (d & 1) ? hc : -hc;
+            const double* Mc = R.M + (size_t)(first + d) * mstride;
+            double px = 1.0;
+            for (int k1 = n1; k1 >= 0; --k1) {      // s_x^(n1-k1) grows as k1 falls
+                double py = 1.0;
+                for (int k2 = n2; k2 >= 0; --k2) {
+                    double pz = 1.0;
+                    for (int k3 = n3; k3 >= 0; --k3) {
+                        const double coef = (double)(c_binom[n1][k1] * c_binom[n2][k2] * c_binom[n3][k3]);
+                        acc += coef * (px * py * pz) * Mc[mindex_dev(k1, k2, k3)];
+                        pz *= sz;
                     }
-                    px *= sx;
+                    py *= sy;
                 }
+                px *= sx;
             }
-            R.M[(size_t)c * mstride + k] = acc;
         }
-        __syncthreads();
+        R.M[(size_t)c * mstride + k] = acc;
     }
 }
 
@@ -422,9 +427,31 @@ void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list) {
 void launch_leaves(hipStream_t s, int nrep, Rep* reps, const int* list) {
     hipLaunchKernelGGL(k_leaves, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
 }
-void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nterms, int mstride) {
-    hipLaunchKernelGGL(k_p2m, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list, nterms, mstride);
-    hipLaunchKernelGGL(k_m2m, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list, nterms, mstride);
+static unsigned chunks(long long items) {
+    long long b = (items + kMomBlock - 1) / kMomBlock;
+    return (unsigned)std::max(1LL, std::min(b, 8192LL));
+}
+
+void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nterms, int mstride,
+                    const Rep* host, const int* host_list) {
+    long long leaf_items = 0;
+    int depth = 0;
+    for (int i = 0; i < nrep; ++i) {
+        const Rep& h = host[host_list[i]];
+        leaf_items = std::max(leaf_items, (long long)h.nleaf * nterms);
+        depth = std::max(depth, h.depth);
+    }
+    hipLaunchKernelGGL(k_p2m, dim3(chunks(leaf_items), nrep), dim3(kMomBlock), 0, s, reps, list, nterms, mstride);
+    for (int level = depth - 1; level >= 0; --level) {
+        long long items = 0;
+        for (int i = 0; i < nrep; ++i) {
+            const Rep& h = host[host_list[i]];
+            if (level < h.depth)
+                items = std::max(items, (long long)(h.level_start[level + 1] - h.level_start[level]) * nterms);
+        }
+        hipLaunchKernelGGL(k_m2m, dim3(chunks(items), nrep), dim3(kMomBlock), 0, s, reps, list, nterms, mstride,
+                           level);
+    }
 }
 
 }  // namespace bhmc

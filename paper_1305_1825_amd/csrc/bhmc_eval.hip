@@ -327,7 +327,8 @@ __device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK>& S, int* cnt2) 
 // the potential at target t from every source except the target's excluded
 // ones; S.err reports an overflowed list or a failed index check;
 // S.overlap / S.coincide report hard-core hits at the overlap target.
-// Returns the number of levels processed (hook is called once per level).
+// Returns the number of levels processed (hook is called once per level,
+// by every thread, right after the level's first loads are issued).
 template <int NTG, int BLOCK, class Hook>
 __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2, Hook&& hook) {
     using TS = Trav<NTG, BLOCK>;
@@ -340,7 +341,6 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
     bool failed = false;
     int level = 0;
     for (; fs > 0 && !failed; ++level) {
-        hook(level);
         int next_n = 0;
         for (int base = 0; base < fs; base += BLOCK) {
             if (far_n > TS::FARCAP - BLOCK) {
@@ -363,12 +363,14 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
             const int fi = (e & kFlagIon) ? 1 : 0, fk = (e & kFlagImg) ? 1 : 0;
             int kind = 0;
             int4 m = make_int4(0, -1, 0, 0);
+            double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (valid && c < R.ncell) { m = R.cm[c]; g = R.cgeo[c]; }
+            // once per level, in the shadow of the loads just issued
+            if (base == 0) hook(level);
             uint32_t cdir = e & kFlagDirect;
             if (valid && c >= R.ncell) {
                 S.err = kErrFrontCell;
             } else if (valid) {
-                m = R.cm[c];
-                const double4 g = R.cgeo[c];
                 const int np = m.x - fi - fk;
                 if (m.y >= 0 && m.y + 8 > R.ncell) {
                     S.err = kErrChildLink;
@@ -969,11 +971,22 @@ struct GradShared {
     int err;
 };
 
+// Sum over the 16 lanes of a row, left in every lane of the row: DPP
+// exchanges within the row (lane ^ 1, lane ^ 2, then the mirror images within
+// 8 and within 16 lanes), no memory traffic.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double row_sum16(double v) {
-    v += __shfl_xor(v, 8, 16);
-    v += __shfl_xor(v, 4, 16);
-    v += __shfl_xor(v, 2, 16);
-    v += __shfl_xor(v, 1, 16);
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
     return v;
 }
 

@@ -42,7 +42,9 @@ void launch_sort(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_count(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_leaves(hipStream_t s, int nrep, Rep* reps, const int* list);
-void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nterms, int mstride);
+// host / host_list: the host mirror of the descriptors (sizes and levels as counted) and the replicas
+void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nterms, int mstride,
+                    const Rep* host, const int* host_list);
 
 // Workspace of one gradient evaluation (device memory, library-owned).
 struct GradWork {
