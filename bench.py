@@ -29,6 +29,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
+# counters on a plain 256 MiB device copy), valid only for the sources they were taken on.
+MEASURED_TRAFFIC = {
+    "csrc": "804c3e003232",
+    "chain": {"moves": 100000, "bytes": 346097770, "l2_hit_rate": 0.9989},
+    "sweep": {"moves": 3038540, "bytes": 295737349168, "l2_hit_rate": 0.6039},
+}
+
 
 def csrc_hash() -> str:
     h = hashlib.sha1()
@@ -38,7 +46,16 @@ def csrc_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def algorithmic_bytes_per_move(c, n_sample=400):
+def traffic(kind, moves):
+    """Measured HBM bytes of one launch of `moves` trial moves, or None when the
+    sources changed since the counters were taken or the launch size differs."""
+    t = MEASURED_TRAFFIC
+    if t["csrc"] != csrc_hash() or t[kind]["moves"] != moves:
+        return None
+    return t[kind]["bytes"]
+
+
+def algorithmic_bytes_per_move(c, n_sample=400, replica=0):
     """Bytes a move must touch at least, from the oracle's interaction counts:
     40 B per visited cell (centre, half side, count, link), 8 B per moment of
     every far cell, 32 B per near source (x, y, z, q), and for an accepted move
@@ -52,7 +69,7 @@ def algorithmic_bytes_per_move(c, n_sample=400):
     tot_v = tot_f = tot_s = 0
     evald = 0
     for m in range(n_sample):
-        i, d, _ = O.draw_move(c["seed"], 0, m, n, c["step"])
+        i, d, _ = O.draw_move(c["seed"], replica, m, n, c["step"])
         rn = np.array([c["x"][i], c["y"][i], c["z"][i]]) + d
         _, reason, cnt = o.delta(i, rn, counts=True)
         if reason == 0:
@@ -101,6 +118,24 @@ def run_plain(c, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return dict(wall=wall, mc_ms=mc_ms, stats=last)
+
+
+def batched_bytes_per_move(R=256, seed=0, sample=8, moves=150):
+    """Algorithmic bytes per trial move of the replica workload: the same count as
+    for the chain on a sample of replicas spread over the size range, weighted by N_r
+    (a sweep makes N_r moves of replica r)."""
+    from paper_1305_1825_amd import workloads as W
+    sizes = [int(v) for v in W.replica_sizes(R, seed=seed)]
+    order = sorted(range(R), key=lambda r: sizes[r])
+    pick = [order[int(k * (R - 1) / (sample - 1))] for k in range(sample)]
+    tot_b = tot_n = 0.0
+    for r in pick:
+        P, x, y, z, q = W.batched_replica(r, sizes[r], seed=seed)
+        c = dict(params=P, x=x, y=y, z=z, q=q, seed=seed, step=1.0)
+        ab = algorithmic_bytes_per_move(c, n_sample=moves, replica=r)
+        tot_b += ab["per_move"] * sizes[r]
+        tot_n += sizes[r]
+    return tot_b / tot_n
 
 
 def run_batched(R, sweeps, seed=0):
@@ -267,7 +302,7 @@ def main():
         "stats": res["stats"],
         "mc_kernel_ms_per_step": mc_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("chain", c["moves"]),
                      "kernel": "k_mc (p=6)", "algorithmic_bytes_per_move": ab["per_move"],
                      "per_move_counts": {k: ab[k] for k in ("visited", "far", "near", "eval_fraction")}},
         "csrc": csrc_hash(),
@@ -276,6 +311,12 @@ def main():
         print("bench: batched replicas", file=sys.stderr, flush=True)
         b = run_batched(256, args.batched_sweeps)
         b["ratio_vs_plain"] = b["moves_per_s"] / value
+        bpm = batched_bytes_per_move()
+        ach = bpm * b["moves_per_s"] / 1e9
+        b["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": traffic("sweep", b["moves"] // b["sweeps"]),
+                         "kernel": "k_mc (p=4), one sweep per launch",
+                         "algorithmic_bytes_per_move": bpm}
         out["batched"] = b
     if not args.no_gradient:
         print("bench: gradient N=1e5", file=sys.stderr, flush=True)
