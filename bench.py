@@ -94,6 +94,7 @@ def run_plain(c, steps, warmup):
     stream = torch.cuda.current_stream()
     mc_ms = []
     last = None
+    final = None
 
     def one_step(timed):
         nonlocal last
@@ -107,6 +108,8 @@ def run_plain(c, steps, warmup):
         if timed:
             mc_ms.append(ev0.elapsed_time(ev1))
         last = st
+        nonlocal final
+        final = [v.cpu().numpy() for v in t.state()]
         t.close()
 
     for _ in range(warmup):
@@ -117,7 +120,7 @@ def run_plain(c, steps, warmup):
         one_step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return dict(wall=wall, mc_ms=mc_ms, stats=last)
+    return dict(wall=wall, mc_ms=mc_ms, stats=last, final=final)
 
 
 def batched_bytes_per_move(R=256, seed=0, sample=8, moves=150):
@@ -224,6 +227,34 @@ def run_large(sweeps, grad_replicas):
                 gradient_s_per_replica=gwall / max(grad_replicas, 1))
 
 
+def accuracy(P, x, y, z, q):
+    """The paper's error measure E of eq. 4.1, sqrt(sum (V_i - V~_i)^2 / sum V_i^2) with
+    V_i = q_i phi_i, and |E_tree - E_dir| / |E_dir|.  The direct sum is the same library at
+    theta = 0 (every cell opened), read from dE/dq_i = l_B phi_i + the exact self-image and
+    central terms."""
+    from paper_1305_1825_amd import bhmc
+    t = bhmc.Tree(P, x, y, z, q)
+    E_tree, phi_t = t.energy(with_phi=True)
+    t.close()
+    d = bhmc.Tree(dict(P, theta=0.0), x, y, z, q)
+    E_dir, _, dq = d.energy_grad()
+    d.close()
+    dq = dq.cpu().numpy()
+    phi_t = phi_t.cpu().numpy()
+    l, a = P["l_B"], P.get("a", 0.0)
+    r2 = x * x + y * y + z * z
+    extra = np.zeros_like(q)
+    if P.get("geom", 0) == 1:
+        if P.get("images", 0):
+            gam = (P["eps_out"] - P["eps_in"]) / (P["eps_out"] + P["eps_in"])
+            extra += l * gam * a * q / (r2 - a * a)
+        extra += l * P.get("Q_center", 0.0) / np.sqrt(r2)
+    phi_d = (dq - extra) / l
+    V, Vt = q * phi_d, q * phi_t
+    return {"E_4_1": float(np.sqrt(np.sum((V - Vt) ** 2) / np.sum(V ** 2))),
+            "E_rel": abs(E_tree - E_dir) / abs(E_dir), "E_tree": E_tree, "E_direct": E_dir}
+
+
 def cpu_baseline(c, seconds=12.0):
     import oracle as O
     P = c["params"]
@@ -318,6 +349,12 @@ def main():
                          "kernel": "k_mc (p=4), one sweep per launch",
                          "algorithmic_bytes_per_move": bpm}
         out["batched"] = b
+    print("bench: accuracy against the direct sum", file=sys.stderr, flush=True)
+    acc = {"start": accuracy(c["params"], c["x"], c["y"], c["z"], c["q"])}
+    if res["final"] is not None:
+        fx, fy, fz, fq = res["final"]
+        acc["end"] = accuracy(c["params"], fx, fy, fz, fq)
+    out["accuracy"] = acc
     if not args.no_gradient:
         print("bench: gradient N=1e5", file=sys.stderr, flush=True)
         out["gradient"] = run_gradient()

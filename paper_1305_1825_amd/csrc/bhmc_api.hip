@@ -176,6 +176,10 @@ static void fill_rep(Rep& r, const bhmc_params& P, int64_t n) {
     r.rmin2 = P.r_min * P.r_min;
     r.rmax2 = P.r_max * P.r_max;
     r.tau2 = P.hard_core * P.hard_core;
+    {
+        const double reach = P.hard_core + 1e-12 * P.box_side;
+        r.reach2 = reach * reach;
+    }
     r.geom = P.geom; r.images = P.images; r.leaf_cap = P.leaf_cap; r.n0 = P.n0;
     r.max_depth = P.max_depth; r.slack = P.slot_slack;
     r.n = (int)n;

@@ -31,6 +31,7 @@ struct Rep {
     double theta2;                 // theta * theta
     double l_B, a, a2, gamma, Qc;  // Bjerrum length, sphere, gamma, central charge
     double rmin2, rmax2, tau2;     // shell walls (squared), hard core squared
+    double reach2;                 // (tau + 1e-12 side)^2: cells within this take the hard-core descent
     double hi[3];                  // lo + side per axis (cube walls)
     int geom, images, leaf_cap, n0, max_depth, slack;
     int n, nsrc;

@@ -278,8 +278,7 @@ __device__ void overlap_below_far(const Rep& R, Trav<NTG, BLOCK>& S, int* cnt2) 
     using TS = Trav<NTG, BLOCK>;
     const int t = S.ovl_t;
     const double x = S.tx[t], y = S.ty[t], z = S.tz[t];
-    const double reach = sqrt(R.tau2) + 1e-12 * R.side;
-    const double reach2 = reach * reach;
+    const double reach2 = R.reach2;
     // n_ovl counts every insert attempt; entries past OVLCAP were never stored
     int cur = 0, fs = S.n_ovl < TS::OVLCAP ? S.n_ovl : TS::OVLCAP;
     for (int j = threadIdx.x; j < fs; j += BLOCK) S.front[0][j] = S.ovl[j];
@@ -384,8 +383,7 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
                         if (mac && np >= R.n0) {
                             kind = (fi | fk) ? 4 : 1;
                             if (t == S.ovl_t) {
-                                const double reach = sqrt(R.tau2) + 1e-12 * R.side;
-                                if (box_dist2(g, S.tx[t], S.ty[t], S.tz[t]) <= reach * reach) {
+                                if (box_dist2(g, S.tx[t], S.ty[t], S.tz[t]) <= R.reach2) {
                                     const int slot = atomicAdd(&S.n_ovl, 1);
                                     if (slot < TS::OVLCAP) S.ovl[slot] = (uint32_t)c; else S.err = kErrStack;
                                 }
