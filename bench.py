@@ -354,6 +354,12 @@ def main():
     if res["final"] is not None:
         fx, fy, fz, fq = res["final"]
         acc["end"] = accuracy(c["params"], fx, fy, fz, fq)
+    # the smallest p at which this workload meets E <= 1e-4, timed the same way on a shorter chain
+    c7 = W.config_colloid_10k(p=7)
+    c7["moves"] = 20000
+    r7 = run_plain(c7, 1, 0)
+    acc["at_1e-4"] = {"p": 7, "moves_per_s": c7["moves"] / (float(np.mean(r7["mc_ms"])) / 1000.0),
+                      "moves": c7["moves"], **accuracy(c7["params"], c7["x"], c7["y"], c7["z"], c7["q"])}
     out["accuracy"] = acc
     if not args.no_gradient:
         print("bench: gradient N=1e5", file=sys.stderr, flush=True)
