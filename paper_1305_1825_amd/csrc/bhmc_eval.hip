@@ -82,9 +82,15 @@ constexpr MiTab make_mi() {
 }
 __constant__ MiTab c_mi = make_mi();
 
+// (n1, n2, n3) of term k packed as n1 | n2 << 8 | n3 << 16; workgroups keep a
+// copy of this table in LDS, so runtime term indices read it there
+__device__ __forceinline__ uint32_t mi_code(int k) {
+    return (uint32_t)c_mi.v[3 * k] | ((uint32_t)c_mi.v[3 * k + 1] << 8) | ((uint32_t)c_mi.v[3 * k + 2] << 16);
+}
+
 // d^n by repeated multiplication (x, then y, then z), as the moments are built
-__device__ __forceinline__ double mono(int k, double dx, double dy, double dz) {
-    const int n1 = c_mi.v[3 * k], n2 = c_mi.v[3 * k + 1], n3 = c_mi.v[3 * k + 2];
+__device__ __forceinline__ double mono(uint32_t code, double dx, double dy, double dz) {
+    const int n1 = (int)(code & 255u), n2 = (int)((code >> 8) & 255u), n3 = (int)(code >> 16);
     double v = 1.0;
     for (int e = 0; e < n1; ++e) v *= dx;
     for (int e = 0; e < n2; ++e) v *= dy;
@@ -192,7 +198,13 @@ struct Trav {
     uint64_t wsum[NW + 1];
     double red[NW][NTG];
     double res[NTG];
+    uint32_t mi[NTERM];              // multi-index of each term, packed (mi_code)
 };
+
+template <int NTG, int BLOCK>
+__device__ __forceinline__ void fill_mi(Trav<NTG, BLOCK>& S) {
+    for (int k = threadIdx.x; k < NTERM; k += BLOCK) S.mi[k] = mi_code(k);
+}
 
 template <int NTG>
 __device__ __forceinline__ void add_to(double (&acc)[NTG], int t, double v) {
@@ -459,8 +471,8 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
         if (c >= R.ncell) { S.err = kErrFlagCell; S.Mx[f][k] = 0.0; continue; }
         const double4 g = R.cgeo[c];
         double mk = R.M[(size_t)c * MSTR + k];
-        if (e & kFlagIon) { const double4 s = S.es_i[t]; mk = mk - s.w * mono(k, s.x - g.x, s.y - g.y, s.z - g.z); }
-        if (e & kFlagImg) { const double4 s = S.es_k[t]; mk = mk - s.w * mono(k, s.x - g.x, s.y - g.y, s.z - g.z); }
+        if (e & kFlagIon) { const double4 s = S.es_i[t]; mk = mk - s.w * mono(S.mi[k], s.x - g.x, s.y - g.y, s.z - g.z); }
+        if (e & kFlagImg) { const double4 s = S.es_k[t]; mk = mk - s.w * mono(S.mi[k], s.x - g.x, s.y - g.y, s.z - g.z); }
         S.Mx[f][k] = mk;
     }
     const int total = near_scan<NTG, BLOCK>(S, near_n);  // its barriers also publish Mx
@@ -542,7 +554,7 @@ __device__ __forceinline__ void prefetch_stage(const Rep& R, McShared& MS, int j
 // cells of the four root paths, applying to each cell, in order, the old ion
 // (-), the new ion (+), the old image (-) and the new image (+).
 template <int BLOCK>
-__device__ __forceinline__ void commit(const Rep& R, McShared& MS, int i) {
+__device__ __forceinline__ void commit(const Rep& R, const Trav<2, BLOCK>& S, McShared& MS, int i) {
     const int tid = threadIdx.x;
     const bool imgs = R.images != 0;
     if (tid == 0) {
@@ -645,7 +657,7 @@ __device__ __forceinline__ void commit(const Rep& R, McShared& MS, int i) {
             for (int jj = 0; jj < 4; ++jj) {
                 if (!(mask & (1 << jj))) continue;
                 const double4 s = MS.contrib[jj];
-                const double v = mono(k, s.x - g.x, s.y - g.y, s.z - g.z);
+                const double v = mono(S.mi[k], s.x - g.x, s.y - g.y, s.z - g.z);
                 if (jj & 1) { m = m + s.w * v; ++dc; } else { m = m - s.w * v; --dc; }
             }
             R.M[(size_t)c * MSTR + k] = m;
@@ -792,7 +804,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     __syncthreads();
     if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
     if (!MS.ok) { out.stop = -6; __syncthreads(); return out; }
-    commit<BLOCK>(R, MS, i);
+    commit<BLOCK>(R, S, MS, i);
     if (MS.err) { out.stop = -8; out.detail = MS.err; }
     out.accepted = 1;
     return out;
@@ -824,6 +836,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
     __shared__ Rep Rs;
     __shared__ int s_r;
     const int tid = threadIdx.x;
+    fill_mi(S);  // published by the first barrier below
     for (;;) {
         if (tid == 0) {
             const int qi = atomicAdd(A.queue, 1);
@@ -868,6 +881,7 @@ __global__ void __launch_bounds__(kMcBlock) k_move(Rep* reps, int r, MoveIO* io)
     __shared__ Trav<2, kMcBlock> S;
     __shared__ McShared MS;
     __shared__ Rep Rs;
+    fill_mi(S);
     load_rep(Rs, reps + r);
     __syncthreads();
     const int i = io->i;
@@ -888,6 +902,7 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
     constexpr int NTG = kEnergyTargets;
     __shared__ Trav<NTG, kEnergyBlock> S;
     __shared__ Rep Rs;
+    fill_mi(S);
     load_rep(Rs, reps + r);
     __syncthreads();
     const int t0 = blockIdx.x * NTG;

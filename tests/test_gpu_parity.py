@@ -113,7 +113,8 @@ def test_build_matches_oracle(case):
 
 
 # ---------------------------------------------------------------- energy change and energy
-@pytest.mark.parametrize("case", ["cube1k", "colloid2k_p6", "colloid_theta0", "colloid_n0"])
+@pytest.mark.parametrize("case", ["cube1k", "colloid2k_p6", "colloid_theta0", "colloid_n0", "colloid_p0",
+                                  "colloid_p10", "cube_p1_theta09"])
 def test_delta_energy_matches_oracle(case):
     if case == "cube1k":
         c, over = W.config_cube_1k(), {}
@@ -121,6 +122,12 @@ def test_delta_energy_matches_oracle(case):
         c, over = W.config_colloid_10k(n=2000), {}
     elif case == "colloid_theta0":
         c, over = W.config_colloid_10k(n=500, p=3), {"theta": 0.0}
+    elif case == "colloid_p0":      # lowest compiled order: monopoles only
+        c, over = W.config_colloid_10k(n=800, p=0), {}
+    elif case == "colloid_p10":     # highest compiled order
+        c, over = W.config_colloid_10k(n=800, p=10), {}
+    elif case == "cube_p1_theta09":  # the widest opening angle
+        c, over = W.config_cube_1k(n=700), {"p": 1, "theta": 0.9}
     else:
         c, over = W.config_colloid_10k(n=1500, p=5), {"n0": 12}
     say("delta", case)
