@@ -495,6 +495,223 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
     return level;
 }
 
+// ------------------------------------------------------------ the move traversal
+// The two targets of a move (the mover's old and new position) exclude the
+// same two sources, so they share every frontier entry: a cell with a 2-bit
+// mask of the targets for which it is still open (bits 24-25), a 2-bit mask of
+// the targets summing every source below it directly by the N_0 rule (bits
+// 26-27) and the two exclusion flags.  Each target takes exactly the decisions
+// of its own traversal.  Far cells are evaluated by lane pairs (lane 2j the
+// old position, 2j+1 the new one) reading the same moment row; near sources by
+// lanes that load a source once and evaluate both targets against it.
+constexpr int kMaskSh = 24, kDirSh = 26;
+
+template <int BLOCK>
+__device__ __forceinline__ void far_pass_mc(const Rep& R, Trav<2, BLOCK>& S, int far_n, int nflag,
+                                            double (&acc)[2]) {
+    static_assert(BLOCK % 2 == 0, "lane pairs");
+    const int t = (int)(threadIdx.x & 1);
+    const int n2 = 2 * (far_n + nflag);
+    for (int j2 = threadIdx.x; j2 < n2; j2 += BLOCK) {
+        const int j = j2 >> 1;
+        const bool fl = j >= far_n;
+        const uint32_t e = fl ? S.flagl[j - far_n] : S.farl[j];
+        if (!((e >> (kMaskSh + t)) & 1u)) continue;
+        const int c = (int)(e & kCellMask);
+        if (c >= R.ncell) { S.err = kErrFarCell; continue; }
+        const double4 g = R.cgeo[c];
+        const double* Mc = fl ? S.Mx[j - far_n]
+                              : (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32);
+        add_to<2>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], Mc));
+    }
+}
+
+// Near leaves of both targets.  For the new position (the overlap target),
+// every ion other than the mover within tau is an overlap.
+template <int BLOCK>
+__device__ __forceinline__ void near_pass_mc(const Rep& R, Trav<2, BLOCK>& S, int near_n, int total,
+                                             double (&acc)[2]) {
+    const int n_ion = R.n;
+    for (int f = threadIdx.x; f < total; f += BLOCK) {
+        int lo = 0, hi = near_n - 1;  // last j with near_pre[j] <= f
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (S.near_pre[mid] <= f) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t e = S.nearl[lo];
+        const uint32_t mask = (e >> kMaskSh) & 3u;
+        const int slot = S.near_base[lo] + (f - S.near_pre[lo]);
+        const double4 s = R.pool4[slot];
+        int sid = -1;
+        if ((e & (kFlagIon | kFlagImg)) || (mask & 2u)) {
+            sid = R.pidx[slot];
+            if (((e & kFlagIon) && sid == S.ex_i[0]) || ((e & kFlagImg) && sid == S.ex_k[0])) continue;
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (!((mask >> t) & 1u)) continue;
+            const double dx = S.tx[t] - s.x, dy = S.ty[t] - s.y, dz = S.tz[t] - s.z;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (t == 1 && sid < n_ion && sid != S.ovl_ex && d2 <= R.tau2) S.overlap = 1;
+            if (d2 == 0.0) { S.coincide = 1; continue; }
+            add_to<2>(acc, t, s.w * rsqrt_nr(d2));
+        }
+    }
+}
+
+// Breadth-first MAC traversal (Sec. 3.2) of the two targets of a move from
+// the root; otherwise as traverse(): deterministic lists, hook once per level,
+// S.res[0..1] the potentials, S.err / S.overlap / S.coincide as there.
+template <int BLOCK, class Hook>
+__device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& hook) {
+    using TS = Trav<2, BLOCK>;
+    constexpr int NW = TS::NW;
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    double acc[2] = {0.0, 0.0};
+    int cur = 0, fs = 1, far_n = 0, near_n = 0, nflag = 0, buf = 0;
+    bool failed = false;
+    int level = 0;
+    for (; fs > 0 && !failed; ++level) {
+        int next_n = 0;
+        for (int base = 0; base < fs; base += BLOCK) {
+            if (far_n > TS::FARCAP - BLOCK) {
+                __syncthreads();
+                far_pass_mc<BLOCK>(R, S, far_n, 0, acc);
+                far_n = 0;
+                __syncthreads();
+            }
+            if (near_n > TS::NEARCAP - BLOCK) {
+                __syncthreads();
+                const int total = near_scan<2, BLOCK>(S, near_n);
+                near_pass_mc<BLOCK>(R, S, near_n, total, acc);
+                near_n = 0;
+                __syncthreads();
+            }
+            const int j = base + tid;
+            const bool valid = j < fs;
+            const uint32_t e = valid ? S.front[cur][j] : 0u;
+            const int c = (int)(e & kCellMask);
+            const int fi = (e & kFlagIon) ? 1 : 0, fk = (e & kFlagImg) ? 1 : 0;
+            const uint32_t open = (e >> kMaskSh) & 3u, dir = (e >> kDirSh) & 3u;
+            int4 m = make_int4(0, -1, 0, 0);
+            double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (valid && c < R.ncell) { m = R.cm[c]; g = R.cgeo[c]; }
+            // once per level, in the shadow of the loads just issued
+            if (base == 0) hook(level);
+            uint32_t farb = 0, nearb = 0, copen = 0, cdir = 0;
+            if (valid && c >= R.ncell) {
+                S.err = kErrFrontCell;
+            } else if (valid) {
+                const int np = m.x - fi - fk;
+                if (m.y >= 0 && m.y + 8 > R.ncell) {
+                    S.err = kErrChildLink;
+                } else if (np > 0) {
+                    // both targets' tests side by side, then the decisions as bit masks
+                    const double dx0 = g.x - S.tx[0], dy0 = g.y - S.ty[0], dz0 = g.z - S.tz[0];
+                    const double dx1 = g.x - S.tx[1], dy1 = g.y - S.ty[1], dz1 = g.z - S.tz[1];
+                    const double d20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
+                    const double d21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
+                    const double h2 = 3.0 * (g.w * g.w);
+                    const uint32_t mac = (h2 <= R.theta2 * d20 ? 1u : 0u) | (h2 <= R.theta2 * d21 ? 2u : 0u);
+                    const bool internal = m.y >= 0;
+                    const uint32_t live = open & ~dir;
+                    farb = live & mac & (np >= R.n0 ? 3u : 0u);
+                    const uint32_t rest = live & ~farb;
+                    copen = rest & ((np > R.n0 && internal) ? 3u : 0u);
+                    nearb = (rest & ~copen & (internal ? 0u : 3u)) | (dir & (internal ? 0u : 3u));
+                    cdir = (rest & ~copen & (internal ? 3u : 0u)) | (dir & (internal ? 3u : 0u));
+                    if ((farb & 2u) && S.ovl_t == 1 && box_dist2(g, S.tx[1], S.ty[1], S.tz[1]) <= R.reach2) {
+                        const int slot = atomicAdd(&S.n_ovl, 1);
+                        if (slot < TS::OVLCAP) S.ovl[slot] = (uint32_t)c; else S.err = kErrStack;
+                    }
+                }
+            }
+            const bool flagged = (fi | fk) != 0;
+            const bool kf = farb && !flagged, kg = farb && flagged, kn = nearb != 0, ks = (copen | cdir) != 0;
+            const uint64_t lt = lanemask_lt();
+            const uint64_t bf = __ballot(kf), bn = __ballot(kn), bs = __ballot(ks), bg = __ballot(kg);
+            if (lane == 0)
+                S.wcnt[buf][w] = (uint64_t)__popcll(bf) | ((uint64_t)__popcll(bn) << 16) |
+                                 ((uint64_t)__popcll(bs) << 32) | ((uint64_t)__popcll(bg) << 48);
+            __syncthreads();
+            uint64_t before = 0, tot = 0;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint64_t v = S.wcnt[buf][ww];
+                before += ww < w ? v : 0ull;
+                tot += v;
+            }
+            buf ^= 1;
+            const int tf = (int)(tot & 0xffff), tn = (int)((tot >> 16) & 0xffff);
+            const int ts = (int)((tot >> 32) & 0xffff), tg = (int)(tot >> 48);
+            if (next_n + 8 * ts > TS::FCAP || nflag + tg > 4) {  // uniform
+                failed = true;
+                break;
+            }
+            const uint32_t flags = e & (kFlagIon | kFlagImg);
+            if (kf) S.farl[far_n + (int)(before & 0xffff) + __popcll(bf & lt)] = (uint32_t)c | (farb << kMaskSh);
+            if (kg) S.flagl[nflag + (int)(before >> 48) + __popcll(bg & lt)] = (uint32_t)c | (farb << kMaskSh) | flags;
+            if (kn) {
+                const int o = near_n + (int)((before >> 16) & 0xffff) + __popcll(bn & lt);
+                S.nearl[o] = (uint32_t)c | (nearb << kMaskSh) | flags;
+                S.near_base[o] = m.z;
+                S.near_pre[o] = m.x;
+                if (m.x < 0 || m.z < 0 || m.z + m.x > R.pool) { S.near_pre[o] = 0; S.err = kErrNearSlots; }
+            }
+            if (ks) {
+                const int o = next_n + 8 * ((int)((before >> 32) & 0xffff) + __popcll(bs & lt));
+                const int dig_i = fi ? key_digit(S.kx_i[0], level + 1) : -1;
+                const int dig_k = fk ? key_digit(S.kx_k[0], level + 1) : -1;
+                const uint32_t masks = (copen << kMaskSh) | (cdir << kDirSh);
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const uint32_t fl = (d == dig_i ? kFlagIon : 0u) | (d == dig_k ? kFlagImg : 0u);
+                    S.front[cur ^ 1][o + d] = (uint32_t)(m.y + d) | masks | fl;
+                }
+            }
+            far_n += tf; near_n += tn; nflag += tg; next_n += 8 * ts;
+        }
+        __syncthreads();  // the next level reads what this one wrote
+        cur ^= 1;
+        fs = next_n;
+    }
+    if (failed) {
+        if (tid == 0) S.err = kErrStack;
+        __syncthreads();
+        return level;
+    }
+    // corrected moments of the far cells that hold an excluded source
+    for (int it = tid; it < nflag * NTERM; it += BLOCK) {
+        const int f = it / NTERM, k = it % NTERM;
+        const uint32_t e = S.flagl[f];
+        const int c = (int)(e & kCellMask);
+        if (c >= R.ncell) { S.err = kErrFlagCell; S.Mx[f][k] = 0.0; continue; }
+        const double4 g = R.cgeo[c];
+        double mk = R.M[(size_t)c * MSTR + k];
+        if (e & kFlagIon) { const double4 s = S.es_i[0]; mk = mk - s.w * mono(S.mi[k], s.x - g.x, s.y - g.y, s.z - g.z); }
+        if (e & kFlagImg) { const double4 s = S.es_k[0]; mk = mk - s.w * mono(S.mi[k], s.x - g.x, s.y - g.y, s.z - g.z); }
+        S.Mx[f][k] = mk;
+    }
+    const int total = near_scan<2, BLOCK>(S, near_n);  // its barriers also publish Mx
+    far_pass_mc<BLOCK>(R, S, far_n, nflag, acc);
+    near_pass_mc<BLOCK>(R, S, near_n, total, acc);
+    __syncthreads();
+    if (S.ovl_t >= 0 && S.n_ovl > 0 && S.err == 0) overlap_below_far<2, BLOCK>(R, S, cnt2);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double sum = wave_sum(acc[k]);
+        if (lane == 0) S.red[w][k] = sum;
+    }
+    __syncthreads();
+    if (tid < 2) {
+        double sum = 0.0;
+        for (int ww = 0; ww < NW; ++ww) sum += S.red[ww][tid];
+        S.res[tid] = sum;
+    }
+    __syncthreads();
+    return level;
+}
+
 // ------------------------------------------------------------ one Monte Carlo move
 constexpr int kMaxPathCells = 4 * kMaxLevels;
 
@@ -694,9 +911,8 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         }
         S.ovl_t = 1; S.ovl_ex = i; S.n_ovl = 0;
         S.err = 0; S.overlap = 0; S.coincide = 0;
-        const uint32_t fl = kFlagIon | (imgs ? kFlagImg : 0u);
-        S.front[0][0] = pack(0, 0, fl);
-        S.front[0][1] = pack(0, 1, fl);
+        // the root, open for both targets
+        S.front[0][0] = (3u << kMaskSh) | kFlagIon | (imgs ? kFlagImg : 0u);
         MS.key[0] = kio;
         MS.key[1] = morton_key(R, rx, ry, rz);
         MS.key[2] = kmo;
@@ -733,7 +949,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         if (tid < nps && MS.plen[tid] == 0 && level < kMaxLevels) step(level);
         if (tid == 64 || tid == 65) prefetch_stage(R, MS, tid - 64, tid == 64 ? i : R.n + i);
     };
-    const int levels = traverse<2, BLOCK>(R, S, 2, MS.cnt2, hook);
+    const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook);
     if (S.err) { out.stop = S.err == kErrStack ? -7 : -8; out.detail = S.err; __syncthreads(); return out; }
     if (tid < nps) {
         for (int level = levels; MS.plen[tid] == 0 && level < kMaxLevels; ++level) step(level);
