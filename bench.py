@@ -85,7 +85,7 @@ def algorithmic_bytes_per_move(c, n_sample=400, replica=0):
                 near=tot_s / max(evald, 1), eval_fraction=frac_eval, commit_bytes=commit)
 
 
-def run_plain(c, steps, warmup):
+def run_plain(c, steps, warmup, tune=True):
     import torch
     from paper_1305_1825_amd import bhmc
     P = c["params"]
@@ -96,9 +96,15 @@ def run_plain(c, steps, warmup):
     last = None
     final = None
 
+    shape = {}
+
     def one_step(timed):
         nonlocal last
         t = bhmc.Tree(P, x, y, z, q)
+        if tune and not shape:  # the warm-up step picks the launch shape, later steps reuse it
+            shape.update(t.autotune(seed=c["seed"], step=c["step"], trial_moves=1000))
+        elif shape:
+            t.set_shape(shape["choice"])
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
@@ -120,7 +126,7 @@ def run_plain(c, steps, warmup):
         one_step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return dict(wall=wall, mc_ms=mc_ms, stats=last, final=final)
+    return dict(wall=wall, mc_ms=mc_ms, stats=last, final=final, autotune=shape)
 
 
 def batched_bytes_per_move(R=256, seed=0, sample=8, moves=150):
@@ -331,6 +337,7 @@ def main():
                                "%d trial moves per step (build included)" % c["moves"],
                    "chain": "plain single chain", "seed": c["seed"]},
         "stats": res["stats"],
+        "autotune": res["autotune"],
         "mc_kernel_ms_per_step": mc_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("chain", c["moves"]),

@@ -210,10 +210,15 @@ bhmc_status bhmc_batch_sweep(bhmc_tree* tree, uint64_t seed, int32_t n_sweeps, d
  * (no moves run yet; EINVAL otherwise) and leaves them exactly as built.
  * choice (nullable, host): the shape kept; ms_host (nullable, host, 3
  * floats): each shape's trial time (0 if not tried: a one-replica handle
- * tries shape 0 only).  The chain of a replica depends on the shape only
+ * tries shapes 0 and 1).  The chain of a replica depends on the shape only
  * through the rounding of its energy sums. */
 bhmc_status bhmc_batch_autotune(bhmc_tree* tree, uint64_t seed, double step, int32_t trial_moves,
                                 int32_t* choice, float* ms_host);
+
+/* Set the Metropolis kernel's launch shape (0, 1 or 2 as for
+ * bhmc_batch_autotune) directly, e.g. to the choice the autotuner made on
+ * another handle of the same workload.  EINVAL for another value. */
+bhmc_status bhmc_set_launch_shape(bhmc_tree* tree, int32_t shape);
 
 /* Gradient of the treecode energy E of bhmc_energy for replica `replica`,
  * exact for the interaction lists its traversal makes (each far pair term

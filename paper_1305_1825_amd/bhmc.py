@@ -71,6 +71,7 @@ SIGNATURES = {
     "bhmc_mc_run": [_v, C.c_int32, C.c_uint64, C.c_uint64, C.c_int64, C.c_double, _v, C.POINTER(Stats)],
     "bhmc_batch_sweep": [_v, C.c_uint64, C.c_int32, C.c_double, C.c_int32, C.POINTER(Stats)],
     "bhmc_batch_autotune": [_v, C.c_uint64, C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)],
+    "bhmc_set_launch_shape": [_v, C.c_int32],
     "bhmc_energy_grad": [_v, C.c_int32, _v, _v, _d],
     "bhmc_get_state": [_v, C.c_int32, _v, _v, _v, _v],
     "bhmc_rebuild": [_v, C.c_int32],
@@ -232,6 +233,9 @@ class Tree:
         ms = (C.c_float * len(self.SHAPES))()
         _check(lib().bhmc_batch_autotune(self.h, seed, step, trial_moves, C.byref(choice), ms), "batch_autotune")
         return dict(choice=int(choice.value), shape=self.SHAPES[choice.value], ms=[float(v) for v in ms])
+
+    def set_shape(self, shape):
+        _check(lib().bhmc_set_launch_shape(self.h, int(shape)), "set_launch_shape")
 
     def energy_grad(self, replica=0):
         torch = _torch()

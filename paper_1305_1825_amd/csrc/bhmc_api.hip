@@ -779,7 +779,7 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
     const int nshape = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
     for (int k = 0; k < nshape && st == BHMC_OK; ++k) {
         const LaunchShape sh = kShapes[k];
-        if (t->R == 1 && !sh.wide) continue;
+        if (t->R == 1 && sh.per_cu > 1) continue;  // one workgroup in all: two per CU is the same shape
         for (int r = 0; r < t->R; ++r) {
             Rep& h = t->host[r];
             h.move_next = 0;
@@ -821,6 +821,20 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
     t->mc_grid = std::max(1, std::min(t->R, kShapes[best].per_cu * ncu));
     t->graph_ok = false;
     if (choice) *choice = best;
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_set_launch_shape(bhmc_tree* t, int32_t shape) {
+    if (!t) return fail(BHMC_EINVAL, "null tree");
+    const int nshape = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+    if (shape < 0 || shape >= nshape) return fail(BHMC_EINVAL, "launch shape %d out of range", shape);
+    int dev = 0, ncu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu <= 0) ncu = 256;
+    t->mc_wide = kShapes[shape].wide;
+    t->mc_grid = std::max(1, std::min(t->R, kShapes[shape].per_cu * ncu));
+    t->graph_ok = false;
     return BHMC_OK;
 }
 
