@@ -714,9 +714,11 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
 
 // ------------------------------------------------------------ one Monte Carlo move
 constexpr int kMaxPathCells = 4 * kMaxLevels;
+constexpr int kPowCells = 24;  // longer path-cell lists build their monomials by repeated products
 
 struct McShared {
     int path[4][kMaxLevels];  // root paths: ion old, ion new, image old, image new
+    double4 path_geo[4][kMaxLevels];  // geometry of each path cell, read with its link
     int plen[4];
     uint64_t key[4];
     double4 contrib[4];       // (position, charge) of the four contributions
@@ -736,6 +738,9 @@ struct McShared {
     int ok;
     int err;
     int cnt2[2];
+    // powers 0..p of each contribution's offset from each of the first kPowCells list cells,
+    // per axis: d^n = x^n1 y^n2 z^n3 by two products
+    double pw[kPowCells][4][3][P + 1];
 };
 
 struct MoveOut { double dE; int reason; int accepted; int stop; int detail; };
@@ -774,6 +779,18 @@ template <int BLOCK>
 __device__ __forceinline__ void commit(const Rep& R, const Trav<2, BLOCK>& S, McShared& MS, int i) {
     const int tid = threadIdx.x;
     const bool imgs = R.images != 0;
+    const bool use_pw = MS.nlist <= kPowCells;
+    if (use_pw) {
+        for (int it = tid; it < MS.nlist * 12; it += BLOCK) {
+            const int li = it / 12, r = it % 12, jj = r / 3, ax = r % 3;
+            const double4 s = MS.contrib[jj], g = MS.list_geo[li];
+            const double d = ax == 0 ? s.x - g.x : (ax == 1 ? s.y - g.y : s.z - g.z);
+            double v = 1.0;
+            MS.pw[li][jj][ax][0] = 1.0;
+            for (int e = 1; e <= P; ++e) { v *= d; MS.pw[li][jj][ax][e] = v; }
+        }
+        __syncthreads();
+    }
     if (tid == 0) {
         // leaf states: cell, base, count of up to four leaves, followed through the moves
         int lc[4], lb[4], ln[4];
@@ -874,7 +891,14 @@ __device__ __forceinline__ void commit(const Rep& R, const Trav<2, BLOCK>& S, Mc
             for (int jj = 0; jj < 4; ++jj) {
                 if (!(mask & (1 << jj))) continue;
                 const double4 s = MS.contrib[jj];
-                const double v = mono(S.mi[k], s.x - g.x, s.y - g.y, s.z - g.z);
+                double v;
+                if (use_pw) {
+                    const uint32_t code = S.mi[k];
+                    v = MS.pw[li][jj][0][code & 255u] * MS.pw[li][jj][1][(code >> 8) & 255u] *
+                        MS.pw[li][jj][2][code >> 16];
+                } else {
+                    v = mono(S.mi[k], s.x - g.x, s.y - g.y, s.z - g.z);
+                }
                 if (jj & 1) { m = m + s.w * v; ++dc; } else { m = m - s.w * v; --dc; }
             }
             R.M[(size_t)c * MSTR + k] = m;
@@ -927,7 +951,9 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     // one step of a root path: descend by the key's digit, or stop at the leaf
     auto step = [&](int level) {
         const int c = MS.path[tid][level];
-        const int link = (c >= 0 && c < R.ncell) ? R.cm[c].y : -1;
+        const bool cok = c >= 0 && c < R.ncell;
+        const int link = cok ? R.cm[c].y : -1;
+        if (cok) MS.path_geo[tid][level] = R.cgeo[c];
         if (c < 0 || c >= R.ncell || (link >= 0 && link + 8 > R.ncell)) {
             MS.err = kErrPathCell;
             MS.plen[tid] = level + 1;
@@ -977,7 +1003,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         const int slot = atomicAdd(&MS.nlist, 1);
         MS.list_cell[slot] = c;
         MS.list_mask[slot] = mask;
-        MS.list_geo[slot] = R.cgeo[c];
+        MS.list_geo[slot] = MS.path_geo[j][l];
     }
     const double po = S.res[0], pn = S.res[1];
     if (S.overlap || S.coincide) { out.reason = 2; __syncthreads(); return out; }
