@@ -156,7 +156,7 @@ def run_batched(R, sweeps, seed=0):
     cat = [torch.as_tensor(np.concatenate([rp[k] for rp in reps]), dtype=torch.float64, device="cuda:0")
            for k in range(1, 5)]
     t = bhmc.Tree(Ps, *cat, n_per_replica=sizes)
-    tune = t.autotune(seed=seed, step=1.0, trial_moves=256)
+    tune = t.autotune(seed=seed, step=1.0, trial_moves=2000)
     t.batch_sweep(seed=seed, n_sweeps=1, step=1.0, use_graph=True)  # warm-up sweep, builds the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -164,8 +164,9 @@ def run_batched(R, sweeps, seed=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     moves = sum(s["moves"] for s in st)
+    rebuilds = sum(s["rebuilds"] for s in st)
     t.close()
-    return dict(moves=moves, wall=wall, moves_per_s=moves / wall, replicas=R, sweeps=sweeps,
+    return dict(moves=moves, wall=wall, moves_per_s=moves / wall, replicas=R, sweeps=sweeps, rebuilds=rebuilds,
                 n_min=min(sizes), n_max=max(sizes), n_total=sum(sizes), autotune=tune)
 
 

@@ -913,7 +913,7 @@ __device__ __forceinline__ void commit(const Rep& R, const Trav<2, BLOCK>& S, Mc
 template <int BLOCK>
 __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double rx,
                             double ry, double rz, double alpha, int mode) {
-    static_assert(BLOCK >= 128, "the commit prefetch runs on the second wave");
+    static_assert(BLOCK >= 128, "the path descents and the commit prefetch run on the last wave");
     const int tid = threadIdx.x;
     MoveOut out{kInf, 0, 0, 0, 0};
     const bool imgs = R.images != 0;
@@ -945,46 +945,53 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         MS.err = 0;
         MS.nlist = 0;
     }
-    if (tid < 4) { MS.path[tid][0] = 0; MS.plen[tid] = 0; }
-    if (tid == 64 || tid == 65) MS.pf_stage[tid - 64] = (tid == 65 && !imgs) ? 3 : 0;
+    // the root-path descents and the commit prefetch run on the last wave, which has no
+    // frontier entries to classify on most levels: lanes 0-3 the paths, lanes 8-9 the prefetch
+    const int th = tid - (BLOCK - 64);
+    if (th >= 0 && th < 4) { MS.path[th][0] = 0; MS.plen[th] = 0; }
+    if (th == 8 || th == 9) MS.pf_stage[th - 8] = (th == 9 && !imgs) ? 3 : 0;
+    int my_level = 0;  // the next level of this lane's root path
     __syncthreads();
     // one step of a root path: descend by the key's digit, or stop at the leaf
-    auto step = [&](int level) {
-        const int c = MS.path[tid][level];
+    auto step = [&](int pj, int level) {
+        const int c = MS.path[pj][level];
         const bool cok = c >= 0 && c < R.ncell;
         const int link = cok ? R.cm[c].y : -1;
-        if (cok) MS.path_geo[tid][level] = R.cgeo[c];
+        if (cok) MS.path_geo[pj][level] = R.cgeo[c];
         if (c < 0 || c >= R.ncell || (link >= 0 && link + 8 > R.ncell)) {
             MS.err = kErrPathCell;
-            MS.plen[tid] = level + 1;
-            MS.path[tid][level] = 0;
+            MS.plen[pj] = level + 1;
+            MS.path[pj][level] = 0;
         } else if (link >= 0 && level + 1 < kMaxLevels) {
-            MS.path[tid][level + 1] = link + key_digit(MS.key[tid], level + 1);
+            MS.path[pj][level + 1] = link + key_digit(MS.key[pj], level + 1);
         } else {
             if (link >= 0) MS.err = kErrPathDepth;
-            MS.plen[tid] = level + 1;
-            if (tid & 1) {  // a new position's leaf: its slot state for the commit
+            MS.plen[pj] = level + 1;
+            if (pj & 1) {  // a new position's leaf: its slot state for the commit
                 const int4 m = R.cm[c];
-                MS.lm_new[tid >> 1] = m;
+                MS.lm_new[pj >> 1] = m;
                 if (m.y >= 0 || m.z < 0 || m.x < 0 || m.z + m.w > R.pool) MS.err = kErrCommitLeaf;
             }
         }
     };
-    // the root paths descend, and the commit state is gathered, one level per traversal level
-    auto hook = [&](int level) {
-        if (tid < nps && MS.plen[tid] == 0 && level < kMaxLevels) step(level);
-        if (tid == 64 || tid == 65) prefetch_stage(R, MS, tid - 64, tid == 64 ? i : R.n + i);
+    // the root paths descend two levels, and the commit state two stages, per traversal level
+    auto hook = [&](int) {
+        if (th >= 0 && th < nps)
+            for (int k = 0; k < 2 && MS.plen[th] == 0 && my_level < kMaxLevels; ++k) step(th, my_level++);
+        if (th == 8 || th == 9)
+            for (int k = 0; k < 2; ++k) prefetch_stage(R, MS, th - 8, th == 8 ? i : R.n + i);
     };
     const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook);
+    (void)levels;
     if (S.err) { out.stop = S.err == kErrStack ? -7 : -8; out.detail = S.err; __syncthreads(); return out; }
-    if (tid < nps) {
-        for (int level = levels; MS.plen[tid] == 0 && level < kMaxLevels; ++level) step(level);
-        if (MS.plen[tid] == 0) { MS.err = kErrPathDepth; MS.plen[tid] = 1; MS.path[tid][0] = 0; }
+    if (th >= 0 && th < nps) {
+        while (MS.plen[th] == 0 && my_level < kMaxLevels) step(th, my_level++);
+        if (MS.plen[th] == 0) { MS.err = kErrPathDepth; MS.plen[th] = 1; MS.path[th][0] = 0; }
     }
-    if (tid == 64 || tid == 65) {
-        const int s = tid == 64 ? i : R.n + i;
-        for (int k = 0; k < 3 && MS.pf_stage[tid - 64] < 3; ++k) prefetch_stage(R, MS, tid - 64, s);
-        if (MS.pf_stage[tid - 64] != 3) MS.err = kErrCommitSlot;
+    if (th == 8 || th == 9) {
+        const int s = th == 8 ? i : R.n + i;
+        for (int k = 0; k < 3 && MS.pf_stage[th - 8] < 3; ++k) prefetch_stage(R, MS, th - 8, s);
+        if (MS.pf_stage[th - 8] != 3) MS.err = kErrCommitSlot;
     }
     __syncthreads();
     if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }

@@ -145,13 +145,16 @@ def replica_sizes(R: int = 256, seed: int = 0, lo: int = 2000, hi: int = 20000):
 
 
 def batched_replica(r: int, n: int, seed: int = 0):
-    """One replica of the batched workload: C1's species and parameters in the
-    a = 10 sphere (eps 2/80, Q_M = 0), shell 10.5 < r < R_r with R_r chosen to
-    keep the cube's number density 1000 / 20^3 = 0.125."""
+    """One replica of the batched workload: the cube workload's species and
+    parameters (+-1, theta 0.5, p 4, leaf 8) in the a = 10 sphere (eps 2/80,
+    Q_M = 0), shell 10.5 < r < R_r with R_r chosen to keep the cube's number
+    density 1000 / 20^3 = 0.125.  Leaf index arrays get three times their
+    build-time fill: over many sweeps +-1 pairs cluster, and a full leaf stops
+    the replica for a rebuild."""
     R_out = (6.0 * n / math.pi + 10.5 ** 3) ** (1.0 / 3.0)
     q = np.concatenate([np.ones(n // 2), -np.ones(n - n // 2)])
     x, y, z, q = shell_system(q, 10.5, R_out, 0.0, seed=seed, tag=4, replica=r)
-    P = shell_params(10.0, 0.0, 10.5, R_out, theta=0.5, p=4, leaf_cap=8)
+    P = shell_params(10.0, 0.0, 10.5, R_out, theta=0.5, p=4, leaf_cap=8, slot_slack=3)
     return P, x, y, z, q
 
 
@@ -165,7 +168,7 @@ def config_gradient_100k(seed: int = 0, n: int = 100000, theta: float = 0.5):
 def config_large_asym(r: int = 0, seed: int = 0, n: int = 199999):
     q = colloid_charges(n, -200.0, z_plus=2, z_minus=1)
     x, y, z, q = shell_system(q, 20.5, 200.0, 0.5, seed=seed, tag=6, replica=r)
-    P = shell_params(20.0, -200.0, 20.5, 200.0, theta=0.5, p=8, leaf_cap=32, hard_core=0.5)
+    P = shell_params(20.0, -200.0, 20.5, 200.0, theta=0.5, p=8, leaf_cap=32, hard_core=0.5, slot_slack=3)
     return dict(name="asym_N%d_p8" % n, params=P, x=x, y=y, z=z, q=q, step=1.0)
 
 
