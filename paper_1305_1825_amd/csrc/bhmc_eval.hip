@@ -560,17 +560,18 @@ __device__ __forceinline__ void near_pass_mc(const Rep& R, Trav<2, BLOCK>& S, in
 }
 
 // Breadth-first MAC traversal (Sec. 3.2) of the two targets of a move from
-// the root; otherwise as traverse(): deterministic lists, hook once per level,
-// S.res[0..1] the potentials, S.err / S.overlap / S.coincide as there.
+// the fs0 entries of level level0 in front[0]; otherwise as traverse():
+// deterministic lists, hook once per level, S.res[0..1] the potentials,
+// S.err / S.overlap / S.coincide as there.
 template <int BLOCK, class Hook>
-__device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& hook) {
+__device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& hook, int fs0, int level0) {
     using TS = Trav<2, BLOCK>;
     constexpr int NW = TS::NW;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
     double acc[2] = {0.0, 0.0};
-    int cur = 0, fs = 1, far_n = 0, near_n = 0, nflag = 0, buf = 0;
+    int cur = 0, fs = fs0, far_n = 0, near_n = 0, nflag = 0, buf = 0;
     bool failed = false;
-    int level = 0;
+    int level = level0;
     for (; fs > 0 && !failed; ++level) {
         int next_n = 0;
         for (int base = 0; base < fs; base += BLOCK) {
@@ -720,6 +721,7 @@ struct McShared {
     int path[4][kMaxLevels];  // root paths: ion old, ion new, image old, image new
     double4 path_geo[4][kMaxLevels];  // geometry of each path cell, read with its link
     int plen[4];
+    int fs0, level0;          // where the move traversal starts
     uint64_t key[4];
     double4 contrib[4];       // (position, charge) of the four contributions
     // commit state gathered while the traversal runs
@@ -935,8 +937,22 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         }
         S.ovl_t = 1; S.ovl_ex = i; S.n_ovl = 0;
         S.err = 0; S.overlap = 0; S.coincide = 0;
-        // the root, open for both targets
-        S.front[0][0] = (3u << kMaskSh) | kFlagIon | (imgs ? kFlagImg : 0u);
+        // The root holds both targets, so the MAC never takes it (theta < 1): it is opened for
+        // both whenever it is split and holds more than N_0 sources besides the two excluded
+        // ones.  Then the traversal starts from its children, cells 1..8 in digit order.
+        const int np_root = R.nsrc - 1 - (imgs ? 1 : 0);
+        if (R.ncell > 1 && np_root > R.n0) {
+            const int di = key_digit(kio, 1), dk = imgs ? key_digit(kmo, 1) : -1;
+            for (int d = 0; d < 8; ++d)
+                S.front[0][d] = (uint32_t)(1 + d) | (3u << kMaskSh) | (d == di ? kFlagIon : 0u) |
+                                (d == dk ? kFlagImg : 0u);
+            MS.fs0 = 8;
+            MS.level0 = 1;
+        } else {
+            S.front[0][0] = (3u << kMaskSh) | kFlagIon | (imgs ? kFlagImg : 0u);
+            MS.fs0 = 1;
+            MS.level0 = 0;
+        }
         MS.key[0] = kio;
         MS.key[1] = morton_key(R, rx, ry, rz);
         MS.key[2] = kmo;
@@ -981,7 +997,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         if (th == 8 || th == 9)
             for (int k = 0; k < 2; ++k) prefetch_stage(R, MS, th - 8, th == 8 ? i : R.n + i);
     };
-    const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook);
+    const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook, MS.fs0, MS.level0);
     (void)levels;
     if (S.err) { out.stop = S.err == kErrStack ? -7 : -8; out.detail = S.err; __syncthreads(); return out; }
     if (th >= 0 && th < nps) {
