@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
 # counters on a plain 256 MiB device copy), valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "csrc": "804c3e003232",
-    "chain": {"moves": 100000, "bytes": 346097770, "l2_hit_rate": 0.9989},
-    "sweep": {"moves": 3038540, "bytes": 295737349168, "l2_hit_rate": 0.6039},
+    "csrc": "00558df1dc50",
+    "chain": {"moves": 100000, "bytes": 347336027, "l2_hit_rate": 0.9984},
+    "sweep": {"moves": 3038540, "bytes": 308587011309, "l2_hit_rate": 0.7211},
 }
 
 
