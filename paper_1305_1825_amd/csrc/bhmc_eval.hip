@@ -716,6 +716,7 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
 // ------------------------------------------------------------ one Monte Carlo move
 constexpr int kMaxPathCells = 4 * kMaxLevels;
 constexpr int kPowCells = 24;  // longer path-cell lists build their monomials by repeated products
+constexpr int kDrawBatch = 64;  // trial moves drawn ahead at once, one per lane of the first wave
 
 struct McShared {
     int path[4][kMaxLevels];  // root paths: ion old, ion new, image old, image new
@@ -724,6 +725,7 @@ struct McShared {
     int fs0, level0;          // where the move traversal starts
     uint64_t key[4];
     double4 contrib[4];       // (position, charge) of the four contributions
+    double alpha;             // the move's Metropolis uniform
     // commit state gathered while the traversal runs
     int2 tr[2];               // tracking (leaf cell, slot) of the ion and of its image
     int4 lm_old[2];           // (count, link, base, cap) of their leaves
@@ -740,6 +742,11 @@ struct McShared {
     int ok;
     int err;
     int cnt2[2];
+    // the next trial moves (index, dx, dy, dz, alpha), and the next mover's ion and image as
+    // loaded while the current move's traversal runs
+    int dr_i[kDrawBatch];
+    double dr_d[kDrawBatch][4];
+    double4 nx_si, nx_mo;
     // powers 0..p of each contribution's offset from each of the first kPowCells list cells,
     // per axis: d^n = x^n1 y^n2 z^n3 by two products
     double pw[kPowCells][4][3][P + 1];
@@ -912,16 +919,18 @@ __device__ __forceinline__ void commit(const Rep& R, const Trav<2, BLOCK>& S, Mc
 
 // mode 0: evaluate; 1: Metropolis with alpha, commit if accepted;
 // 2: commit unless rejected by a wall or an overlap.
+//
+// si and mo are the mover's ion and image as stored (mo unused without images);
+// inext >= 0 names the next move's ion, whose sources one lane loads into
+// MS.nx_si / MS.nx_mo during the traversal (valid if the ion is not i).
 template <int BLOCK>
-__device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double rx,
-                            double ry, double rz, double alpha, int mode) {
+__device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double4 si,
+                            double4 mo, double rx, double ry, double rz, double alpha, int mode, int inext) {
     static_assert(BLOCK >= 128, "the path descents and the commit prefetch run on the last wave");
     const int tid = threadIdx.x;
     MoveOut out{kInf, 0, 0, 0, 0};
     const bool imgs = R.images != 0;
     const int nps = imgs ? 4 : 2;
-    const double4 si = R.src[i];
-    const double4 mo = imgs ? R.src[R.n + i] : make_double4(0, 0, 0, 0);
     if (outside(R, rx, ry, rz)) { out.reason = 1; return out; }
     if (tid == 0) {
         const double4 sn = make_double4(rx, ry, rz, si.w);
@@ -958,6 +967,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         MS.key[2] = kmo;
         MS.key[3] = imgs ? morton_key(R, mn.x, mn.y, mn.z) : 0;
         MS.contrib[0] = si; MS.contrib[1] = sn; MS.contrib[2] = mo; MS.contrib[3] = mn;
+        MS.alpha = alpha;
         MS.err = 0;
         MS.nlist = 0;
     }
@@ -990,12 +1000,19 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
             }
         }
     };
-    // the root paths descend two levels, and the commit state two stages, per traversal level
-    auto hook = [&](int) {
+    // the root paths descend two levels, and the commit state two stages, per traversal level;
+    // on the first level, whose at most 8 entries sit on the first wave, the first lane of the
+    // second-to-last wave loads the next mover's sources (a lane of its own wave: divergent
+    // lanes of one wave would wait for their loads one after another)
+    auto hook = [&](int level) {
         if (th >= 0 && th < nps)
             for (int k = 0; k < 2 && MS.plen[th] == 0 && my_level < kMaxLevels; ++k) step(th, my_level++);
         if (th == 8 || th == 9)
             for (int k = 0; k < 2; ++k) prefetch_stage(R, MS, th - 8, th == 8 ? i : R.n + i);
+        if (th == -64 && level == MS.level0 && inext >= 0) {
+            MS.nx_si = R.src[inext];
+            MS.nx_mo = imgs ? R.src[R.n + inext] : make_double4(0, 0, 0, 0);
+        }
     };
     const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook, MS.fs0, MS.level0);
     (void)levels;
@@ -1030,17 +1047,19 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     }
     const double po = S.res[0], pn = S.res[1];
     if (S.overlap || S.coincide) { out.reason = 2; __syncthreads(); return out; }
-    const double q = si.w, l = R.l_B;
+    // the move's positions and alpha come back from LDS: no registers held across the traversal
+    const double4 so = MS.contrib[0], sn = MS.contrib[1];
+    const double q = so.w, l = R.l_B;
     double dE = l * q * (pn - po);
     if (R.geom == 1) {
-        const double rn2 = rx * rx + ry * ry + rz * rz;
-        const double ro2 = si.x * si.x + si.y * si.y + si.z * si.z;
+        const double rn2 = sn.x * sn.x + sn.y * sn.y + sn.z * sn.z;
+        const double ro2 = so.x * so.x + so.y * so.y + so.z * so.z;
         if (imgs) dE += 0.5 * l * R.gamma * R.a * q * q * (1.0 / (rn2 - R.a2) - 1.0 / (ro2 - R.a2));
         if (R.Qc != 0.0) dE += l * R.Qc * q * (1.0 / sqrt(rn2) - 1.0 / sqrt(ro2));
     }
     out.dE = dE;
     bool acc = false;
-    if (mode == 1) acc = dE <= 0.0 || alpha <= exp(-dE);
+    if (mode == 1) acc = dE <= 0.0 || MS.alpha <= exp(-dE);
     else if (mode == 2) acc = true;
     if (!acc) { __syncthreads(); return out; }
     if (tid == 0) {
@@ -1113,14 +1132,35 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
         load_rep(Rs, reps + r);
         __syncthreads();
         long long m = Rs.move_next;
-        const long long mend = Rs.move_end;
+        const long long m0 = m, mend = Rs.move_end;
+        const bool imgs = Rs.images != 0;
         long long st_moves = 0, st_acc = 0, st_wall = 0, st_ovl = 0, st_met = 0;
         int status = 0, detail = 0;
+        int prev_i = -1;
+        bool have_nx = false;  // MS.nx_si / nx_mo hold this move's sources as of the last move
         for (; m < mend; ++m) {
-            const Draw d = draw_move(A.seed, (uint32_t)r, (uint64_t)m, Rs.n, A.step);
-            const double4 si = Rs.src[d.i];
-            const MoveOut o = one_move<BLOCK>(Rs, S, MS, d.i, si.x + d.dx, si.y + d.dy,
-                                                 si.z + d.dz, d.alpha, 1);
+            const int b = (int)((m - m0) & (kDrawBatch - 1));
+            if (b == 0) {
+                // the first wave draws the next kDrawBatch moves, one per lane
+                if (tid < kDrawBatch && m + tid < mend) {
+                    const Draw d = draw_move(A.seed, (uint32_t)r, (uint64_t)(m + tid), Rs.n, A.step);
+                    MS.dr_i[tid] = d.i;
+                    MS.dr_d[tid][0] = d.dx; MS.dr_d[tid][1] = d.dy; MS.dr_d[tid][2] = d.dz;
+                    MS.dr_d[tid][3] = d.alpha;
+                }
+                __syncthreads();
+            }
+            const int i = MS.dr_i[b];
+            const int inext = (b + 1 < kDrawBatch && m + 1 < mend) ? MS.dr_i[b + 1] : -1;
+            // the last move changed only its own ion and image
+            const bool use_nx = have_nx && i != prev_i;
+            const double4 si = use_nx ? MS.nx_si : Rs.src[i];
+            const double4 mo = use_nx ? MS.nx_mo : (imgs ? Rs.src[Rs.n + i] : make_double4(0, 0, 0, 0));
+            const MoveOut o = one_move<BLOCK>(Rs, S, MS, i, si, mo, si.x + MS.dr_d[b][0], si.y + MS.dr_d[b][1],
+                                              si.z + MS.dr_d[b][2], MS.dr_d[b][3], 1, inext);
+            // a move outside the walls returns before its traversal, so before the load
+            have_nx = inext >= 0 && o.reason != 1;
+            prev_i = i;
             if (o.stop) { status = o.stop; detail = o.detail; break; }
             ++st_moves;
             if (o.accepted) ++st_acc;
@@ -1150,8 +1190,10 @@ __global__ void __launch_bounds__(kMcBlock) k_move(Rep* reps, int r, MoveIO* io)
     load_rep(Rs, reps + r);
     __syncthreads();
     const int i = io->i;
-    const MoveOut o = one_move<kMcBlock>(Rs, S, MS, i, io->rn[0], io->rn[1], io->rn[2], 0.0,
-                                         io->mode == 0 ? 0 : 2);
+    const double4 si = Rs.src[i];
+    const double4 mo = Rs.images ? Rs.src[Rs.n + i] : make_double4(0, 0, 0, 0);
+    const MoveOut o = one_move<kMcBlock>(Rs, S, MS, i, si, mo, io->rn[0], io->rn[1], io->rn[2], 0.0,
+                                         io->mode == 0 ? 0 : 2, -1);
     if (threadIdx.x == 0) {
         io->dE = o.dE;
         io->reason = o.reason;

@@ -48,3 +48,7 @@ def test_null_inputs_rejected():
     assert bhmc.lib().bhmc_build(C.byref(pp), 10, None, None, None, None, None, C.byref(h)) == -1
     assert bhmc.lib().bhmc_build(C.byref(pp), 0, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1),
                                  C.c_void_p(1), None, C.byref(h)) == -1
+    # one past the largest ion count a handle takes
+    assert bhmc.lib().bhmc_build(C.byref(pp), (1 << 22) + 1, C.c_void_p(1), C.c_void_p(1), C.c_void_p(1),
+                                 C.c_void_p(1), None, C.byref(h)) == -1
+    assert b"2^22" in bhmc.lib().bhmc_last_error()

@@ -78,3 +78,24 @@ def test_large_replica_first_moves_p8():
     first = np.nonzero(bits != ro["accept"])[0]
     assert len(first) == 0, "accept streams part at move %d" % first[0]
     assert same_positions(g.state(1), o, n)
+
+
+def test_maximum_ion_count_with_images():
+    """The largest system a handle takes: 2^22 ions plus their 2^22 Kelvin
+    images (2^23 sources, a 16-level tree); the first trial moves of its
+    chain must match the oracle bit for bit."""
+    n = 1 << 22
+    q = W.colloid_charges(n, -1000.0)
+    x, y, z, q = W.shell_system(q, 20.5, 400.0, 0.0, seed=0, tag=9)
+    P = W.shell_params(20.0, -1000.0, 20.5, 400.0, theta=0.5, p=2, leaf_cap=16, l_B=1.0)
+    say("2^22 ions + images, p=2, 300 moves")
+    g = bhmc.Tree(P, x, y, z, q)
+    rg = g.mc_run(seed=0, n_moves=300, step=1.0, accept_bits=True)
+    o = O.Tree(P, x, y, z, q)
+    ro = o.mc_run(seed=0, replica=0, move0=0, n_moves=300, step=1.0)
+    bits = rg["accept"].cpu().numpy()
+    first = np.nonzero(bits != ro["accept"])[0]
+    assert len(first) == 0, "accept streams part at move %d" % first[0]
+    assert rg["accepted"] == ro["stats"][0] and rg["rejected_wall"] == ro["stats"][1]
+    assert same_positions(g.state(), o, n)
+    g.close()
