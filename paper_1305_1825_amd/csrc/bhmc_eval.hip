@@ -926,7 +926,8 @@ __device__ __forceinline__ void commit(const Rep& R, const Trav<2, BLOCK>& S, Mc
 template <int BLOCK>
 __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double4 si,
                             double4 mo, double rx, double ry, double rz, double alpha, int mode, int inext) {
-    static_assert(BLOCK >= 128, "the path descents and the commit prefetch run on the last wave");
+    static_assert(BLOCK >= 256, "the path descents, the commit prefetch and the next mover's load run on "
+                                "the last three waves");
     const int tid = threadIdx.x;
     MoveOut out{kInf, 0, 0, 0, 0};
     const bool imgs = R.images != 0;
@@ -971,11 +972,14 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         MS.err = 0;
         MS.nlist = 0;
     }
-    // the root-path descents and the commit prefetch run on the last wave, which has no
-    // frontier entries to classify on most levels: lanes 0-3 the paths, lanes 8-9 the prefetch
-    const int th = tid - (BLOCK - 64);
+    // work beside the traversal runs on the last waves, which have no frontier entries to
+    // classify on most levels, each task on a wave of its own (divergent lanes of one wave
+    // would wait for their loads one after another): the root-path descents on lanes 0-3 of
+    // the last wave, the commit prefetch on lanes 0-1 of the wave before it, and the next
+    // mover's load on lane 0 of the wave before that
+    const int th = tid - (BLOCK - 64), tp = tid - (BLOCK - 128);
     if (th >= 0 && th < 4) { MS.path[th][0] = 0; MS.plen[th] = 0; }
-    if (th == 8 || th == 9) MS.pf_stage[th - 8] = (th == 9 && !imgs) ? 3 : 0;
+    if (tp == 0 || tp == 1) MS.pf_stage[tp] = (tp == 1 && !imgs) ? 3 : 0;
     int my_level = 0;  // the next level of this lane's root path
     __syncthreads();
     // one step of a root path: descend by the key's digit, or stop at the leaf
@@ -1001,15 +1005,13 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         }
     };
     // the root paths descend two levels, and the commit state two stages, per traversal level;
-    // on the first level, whose at most 8 entries sit on the first wave, the first lane of the
-    // second-to-last wave loads the next mover's sources (a lane of its own wave: divergent
-    // lanes of one wave would wait for their loads one after another)
+    // the next mover's sources are loaded on the first level
     auto hook = [&](int level) {
         if (th >= 0 && th < nps)
             for (int k = 0; k < 2 && MS.plen[th] == 0 && my_level < kMaxLevels; ++k) step(th, my_level++);
-        if (th == 8 || th == 9)
-            for (int k = 0; k < 2; ++k) prefetch_stage(R, MS, th - 8, th == 8 ? i : R.n + i);
-        if (th == -64 && level == MS.level0 && inext >= 0) {
+        if (tp == 0 || tp == 1)
+            for (int k = 0; k < 2; ++k) prefetch_stage(R, MS, tp, tp == 0 ? i : R.n + i);
+        if (tp == -64 && level == MS.level0 && inext >= 0) {
             MS.nx_si = R.src[inext];
             MS.nx_mo = imgs ? R.src[R.n + inext] : make_double4(0, 0, 0, 0);
         }
@@ -1021,10 +1023,10 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         while (MS.plen[th] == 0 && my_level < kMaxLevels) step(th, my_level++);
         if (MS.plen[th] == 0) { MS.err = kErrPathDepth; MS.plen[th] = 1; MS.path[th][0] = 0; }
     }
-    if (th == 8 || th == 9) {
-        const int s = th == 8 ? i : R.n + i;
-        for (int k = 0; k < 3 && MS.pf_stage[th - 8] < 3; ++k) prefetch_stage(R, MS, th - 8, s);
-        if (MS.pf_stage[th - 8] != 3) MS.err = kErrCommitSlot;
+    if (tp == 0 || tp == 1) {
+        const int s = tp == 0 ? i : R.n + i;
+        for (int k = 0; k < 3 && MS.pf_stage[tp] < 3; ++k) prefetch_stage(R, MS, tp, s);
+        if (MS.pf_stage[tp] != 3) MS.err = kErrCommitSlot;
     }
     __syncthreads();
     if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
