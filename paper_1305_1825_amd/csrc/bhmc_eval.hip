@@ -117,10 +117,20 @@ __device__ __forceinline__ void t_step(double (&T)[N], double Rx, double Ry, dou
     else T[K] = -(A * f) * ir2;
 }
 
+// Moment rows are read through pointers qualified with their address space:
+// global (HBM) rows then compile to global loads and LDS rows to LDS loads, each
+// waited for by its own counter, so several of a row's loads are in flight at
+// once.  Through a generic pointer they become flat loads, each waited for in
+// full before the next is issued.
+using GRow = const __attribute__((address_space(1))) double*;
+using LRow = const __attribute__((address_space(3))) double*;
+__device__ __forceinline__ GRow grow(const double* p) { return (GRow)p; }
+__device__ __forceinline__ LRow lrow(const double* p) { return (LRow)p; }
+
 // sum_n T_n M^n, each T_n folded into the sum as soon as it exists
-template <int K>
+template <int K, class MP>
 __device__ __forceinline__ void far_rec(double (&T)[NTERM], double Rx, double Ry, double Rz,
-                                        double ir2, const double* __restrict__ Mc, double& acc) {
+                                        double ir2, MP __restrict__ Mc, double& acc) {
     if constexpr (K < NTERM) {
         if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
         acc = fma(T[K], Mc[K], acc);
@@ -128,7 +138,8 @@ __device__ __forceinline__ void far_rec(double (&T)[NTERM], double Rx, double Ry
     }
 }
 
-__device__ __forceinline__ double far_eval(double Rx, double Ry, double Rz, const double* Mc) {
+template <class MP>
+__device__ __forceinline__ double far_eval(double Rx, double Ry, double Rz, MP Mc) {
     const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
     double T[NTERM];
     T[0] = rsqrt_nr(r2);
@@ -213,20 +224,24 @@ __device__ __forceinline__ void add_to(double (&acc)[NTG], int t, double v) {
         if (k == t) acc[k] += v;
 }
 
-// Far cells, plus (index >= far_n) the cells holding an excluded source whose
-// corrected moments sit in LDS.
+// Far cells, then the cells holding an excluded source, whose corrected
+// moments sit in LDS.
 template <int NTG, int BLOCK>
 __device__ __forceinline__ void far_pass(const Rep& R, Trav<NTG, BLOCK>& S, int far_n, int nflag,
                                          double (&acc)[NTG]) {
-    for (int j = threadIdx.x; j < far_n + nflag; j += BLOCK) {
-        const bool fl = j >= far_n;
-        const uint32_t e = fl ? S.flagl[j - far_n] : S.farl[j];
+    for (int j = threadIdx.x; j < far_n; j += BLOCK) {
+        const uint32_t e = S.farl[j];
         const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
         if (c >= R.ncell) { S.err = kErrFarCell; continue; }
         const double4 g = R.cgeo[c];
-        const double* Mc = fl ? S.Mx[j - far_n]
-                              : (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32);
-        add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], Mc));
+        add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], grow(R.M + (size_t)c * MSTR)));
+    }
+    for (int j = threadIdx.x; j < nflag; j += BLOCK) {
+        const uint32_t e = S.flagl[j];
+        const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
+        if (c >= R.ncell) { S.err = kErrFarCell; continue; }
+        const double4 g = R.cgeo[c];
+        add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], lrow(S.Mx[j])));
     }
 }
 
@@ -511,18 +526,22 @@ __device__ __forceinline__ void far_pass_mc(const Rep& R, Trav<2, BLOCK>& S, int
                                             double (&acc)[2]) {
     static_assert(BLOCK % 2 == 0, "lane pairs");
     const int t = (int)(threadIdx.x & 1);
-    const int n2 = 2 * (far_n + nflag);
-    for (int j2 = threadIdx.x; j2 < n2; j2 += BLOCK) {
-        const int j = j2 >> 1;
-        const bool fl = j >= far_n;
-        const uint32_t e = fl ? S.flagl[j - far_n] : S.farl[j];
+    for (int j2 = threadIdx.x; j2 < 2 * far_n; j2 += BLOCK) {
+        const uint32_t e = S.farl[j2 >> 1];
         if (!((e >> (kMaskSh + t)) & 1u)) continue;
         const int c = (int)(e & kCellMask);
         if (c >= R.ncell) { S.err = kErrFarCell; continue; }
         const double4 g = R.cgeo[c];
-        const double* Mc = fl ? S.Mx[j - far_n]
-                              : (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32);
-        add_to<2>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], Mc));
+        add_to<2>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], grow(R.M + (size_t)c * MSTR)));
+    }
+    // the cells holding an excluded source, with their corrected moments in LDS
+    for (int j2 = threadIdx.x; j2 < 2 * nflag; j2 += BLOCK) {
+        const uint32_t e = S.flagl[j2 >> 1];
+        if (!((e >> (kMaskSh + t)) & 1u)) continue;
+        const int c = (int)(e & kCellMask);
+        if (c >= R.ncell) { S.err = kErrFarCell; continue; }
+        const double4 g = R.cgeo[c];
+        add_to<2>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], lrow(S.Mx[j2 >> 1])));
     }
 }
 
@@ -1314,9 +1333,9 @@ __device__ __forceinline__ double row_sum16(double v) {
 
 // T up to order p + 1 for one (far cell, target) pair of a row: P and F for
 // the lane's target; the row's sum of w T_n goes to L, term K by lane K mod 16.
-template <int K>
+template <int K, class MP>
 __device__ __forceinline__ void far_rec_row(double (&T)[NTERM1], double Rx, double Ry, double Rz, double ir2,
-                                            const double* __restrict__ Mc, double* __restrict__ Lc, double w,
+                                            MP __restrict__ Mc, double* __restrict__ Lc, double w,
                                             int k, double& phi, double& fx, double& fy, double& fz) {
     if constexpr (K < NTERM1) {
         constexpr TEnt e = TT1.e[K];
@@ -1380,7 +1399,7 @@ __device__ __forceinline__ void grad_rows(const Rep& R, GradShared& S, int far_n
         T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
         const double ir2 = T[0] * T[0];
         double phi = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-        far_rec_row<0>(T, Rx, Ry, Rz, ir2, (const double*)__builtin_assume_aligned(R.M + (size_t)c * MSTR, 32),
+        far_rec_row<0>(T, Rx, Ry, Rz, ir2, grow(R.M + (size_t)c * MSTR),
                        L + (size_t)c * MSTR, act ? wk : 0.0, k, phi, fx, fy, fz);
         if (act) { acc[0] += phi; acc[1] += fx; acc[2] += fy; acc[3] += fz; }
     }
