@@ -127,6 +127,23 @@ using LRow = const __attribute__((address_space(3))) double*;
 __device__ __forceinline__ GRow grow(const double* p) { return (GRow)p; }
 __device__ __forceinline__ LRow lrow(const double* p) { return (LRow)p; }
 
+// The same for single records of the tree in HBM: cell geometry, cell header,
+// a source, a slot's source index, a tracking entry.
+using GInt = const __attribute__((address_space(1))) int*;
+__device__ __forceinline__ double4 gload(const double4* p) {
+    const GRow q = (GRow)(const double*)p;
+    return make_double4(q[0], q[1], q[2], q[3]);
+}
+__device__ __forceinline__ int4 gload(const int4* p) {
+    const GInt q = (GInt)(const int*)p;
+    return make_int4(q[0], q[1], q[2], q[3]);
+}
+__device__ __forceinline__ int2 gload(const int2* p) {
+    const GInt q = (GInt)(const int*)p;
+    return make_int2(q[0], q[1]);
+}
+__device__ __forceinline__ int gload(const int* p) { return *(GInt)p; }
+
 // sum_n T_n M^n, each T_n folded into the sum as soon as it exists
 template <int K, class MP>
 __device__ __forceinline__ void far_rec(double (&T)[NTERM], double Rx, double Ry, double Rz,
@@ -560,10 +577,10 @@ __device__ __forceinline__ void near_pass_mc(const Rep& R, Trav<2, BLOCK>& S, in
         const uint32_t e = S.nearl[lo];
         const uint32_t mask = (e >> kMaskSh) & 3u;
         const int slot = S.near_base[lo] + (f - S.near_pre[lo]);
-        const double4 s = R.pool4[slot];
+        const double4 s = gload(R.pool4 + slot);
         int sid = -1;
         if ((e & (kFlagIon | kFlagImg)) || (mask & 2u)) {
-            sid = R.pidx[slot];
+            sid = gload(R.pidx + slot);
             if (((e & kFlagIon) && sid == S.ex_i[0]) || ((e & kFlagImg) && sid == S.ex_k[0])) continue;
         }
 #pragma unroll
@@ -615,7 +632,7 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
             const uint32_t open = (e >> kMaskSh) & 3u, dir = (e >> kDirSh) & 3u;
             int4 m = make_int4(0, -1, 0, 0);
             double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (valid && c < R.ncell) { m = R.cm[c]; g = R.cgeo[c]; }
+            if (valid && c < R.ncell) { m = gload(R.cm + c); g = gload(R.cgeo + c); }
             // once per level, in the shadow of the loads just issued
             if (base == 0) hook(level);
             uint32_t farb = 0, nearb = 0, copen = 0, cdir = 0;
@@ -779,20 +796,20 @@ constexpr double kInf = __builtin_huge_val();
 __device__ __forceinline__ void prefetch_stage(const Rep& R, McShared& MS, int j, int s) {
     const int stage = MS.pf_stage[j];
     if (stage == 0) {
-        const int2 t = R.track[s];
+        const int2 t = gload(R.track + s);
         MS.tr[j] = t;
         MS.pf_stage[j] = (t.x >= 0 && t.x < R.ncell) ? 1 : 9;
     } else if (stage == 1) {
-        const int4 m = R.cm[MS.tr[j].x];
+        const int4 m = gload(R.cm + MS.tr[j].x);
         MS.lm_old[j] = m;
         const bool sane = m.y < 0 && m.x >= 1 && m.z >= 0 && m.z + m.x <= R.pool && m.x <= m.w &&
                           MS.tr[j].y >= 0 && MS.tr[j].y < m.x;
         MS.pf_stage[j] = sane ? 2 : 9;
     } else if (stage == 2) {
         const int4 m = MS.lm_old[j];
-        MS.last_pidx[j] = R.pidx[m.z + m.x - 1];
-        MS.last_pool[j] = R.pool4[m.z + m.x - 1];
-        MS.self_pidx[j] = R.pidx[m.z + MS.tr[j].y];
+        MS.last_pidx[j] = gload(R.pidx + m.z + m.x - 1);
+        MS.last_pool[j] = gload(R.pool4 + m.z + m.x - 1);
+        MS.self_pidx[j] = gload(R.pidx + m.z + MS.tr[j].y);
         MS.pf_stage[j] = 3;
     }
 }
@@ -1005,8 +1022,8 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     auto step = [&](int pj, int level) {
         const int c = MS.path[pj][level];
         const bool cok = c >= 0 && c < R.ncell;
-        const int link = cok ? R.cm[c].y : -1;
-        if (cok) MS.path_geo[pj][level] = R.cgeo[c];
+        const int link = cok ? gload(R.cm + c).y : -1;
+        if (cok) MS.path_geo[pj][level] = gload(R.cgeo + c);
         if (c < 0 || c >= R.ncell || (link >= 0 && link + 8 > R.ncell)) {
             MS.err = kErrPathCell;
             MS.plen[pj] = level + 1;
@@ -1017,7 +1034,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
             if (link >= 0) MS.err = kErrPathDepth;
             MS.plen[pj] = level + 1;
             if (pj & 1) {  // a new position's leaf: its slot state for the commit
-                const int4 m = R.cm[c];
+                const int4 m = gload(R.cm + c);
                 MS.lm_new[pj >> 1] = m;
                 if (m.y >= 0 || m.z < 0 || m.x < 0 || m.z + m.w > R.pool) MS.err = kErrCommitLeaf;
             }
