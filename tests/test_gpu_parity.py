@@ -198,6 +198,42 @@ def test_mc_chain_bit_exact(case):
     assert_moments(cg, co, cell_map(cg), cell_map(co), o, P["p"], rtol=1e-11)
 
 
+@pytest.mark.parametrize("case", ["cube_n4", "shell_n3_images", "cube_n40_leaf1"])
+def test_mc_chain_few_ions(case):
+    """Chains on a handful of ions: the same ion is drawn twice in a row on
+    about every fourth move (the next mover's sources must then come from the
+    committed move, not from the load made during it), chains of 700 moves
+    cross several batches of drawn moves, and a one-cell tree starts its
+    traversal at the root."""
+    if case == "cube_n4":
+        P = W.make_params(box_side=6.0, p=3, leaf_cap=8, l_B=1.0, hard_core=0.3)
+        x, y, z, q = [1.0, 2.0, 4.0, 5.0], [1.0, 4.5, 2.0, 5.0], [1.0, 3.0, 5.0, 2.0], [1.0, -1.0, 1.0, -1.0]
+    elif case == "shell_n3_images":
+        P = W.shell_params(5.0, -3.0, 5.5, 12.0, p=4, leaf_cap=2, l_B=2.0, hard_core=0.5)
+        x, y, z, q = [7.0, -6.0, 0.5], [0.5, 6.5, -8.0], [1.0, -2.0, 3.0], [1.0, 1.0, 1.0]
+    else:
+        c = W.config_cube_1k(n=40)
+        P = dict(c["params"], leaf_cap=1, p=5)
+        x, y, z, q = c["x"], c["y"], c["z"], c["q"]
+    say("few-ion chain", case)
+    g = bhmc.Tree(P, x, y, z, q)
+    o = O.Tree(P, x, y, z, q)
+    moves = 700
+    rg = g.mc_run(seed=3, n_moves=moves, step=1.5, accept_bits=True)
+    ro = o.mc_run(seed=3, replica=0, move0=0, n_moves=moves, step=1.5)
+    bits = rg["accept"].cpu().numpy()
+    first = np.nonzero(bits != ro["accept"])[0]
+    assert len(first) == 0, "accept streams part at move %d" % first[0]
+    st = ro["stats"]
+    assert rg["accepted"] == st[0] and rg["rejected_wall"] == st[1] and rg["rejected_overlap"] == st[2]
+    assert st[0] > 50
+    n = len(x)
+    xs, ys, zs, _ = (t.cpu().numpy() for t in g.state())
+    xo, yo, zo, _ = o.sources()
+    assert np.array_equal(xs, xo[:n]) and np.array_equal(ys, yo[:n]) and np.array_equal(zs, zo[:n])
+    assert_same_slots(g, o)
+
+
 def test_commit_move_api_and_errors():
     c = W.config_colloid_10k(n=800, p=4)
     P, g, o = both(c)
