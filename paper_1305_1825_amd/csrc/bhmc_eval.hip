@@ -597,11 +597,13 @@ __device__ __forceinline__ void near_pass_mc(const Rep& R, Trav<2, BLOCK>& S, in
 
 // Breadth-first MAC traversal (Sec. 3.2) of the two targets of a move from
 // the fs0 entries of level level0 in front[0]; otherwise as traverse():
-// deterministic lists, hook once per level, S.res[0..1] the potentials,
-// S.err / S.overlap / S.coincide as there.
+// deterministic lists, hook once per level, res[0..1] the potentials (the
+// same in every thread), S.err / S.overlap / S.coincide as there.
 template <int BLOCK, class Hook>
-__device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& hook, int fs0, int level0) {
+__device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& hook, int fs0, int level0,
+                           double (&res)[2]) {
     using TS = Trav<2, BLOCK>;
+    res[0] = res[1] = 0.0;
     constexpr int NW = TS::NW;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
     double acc[2] = {0.0, 0.0};
@@ -732,20 +734,20 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
     const int total = near_scan<2, BLOCK>(S, near_n);  // its barriers also publish Mx
     far_pass_mc<BLOCK>(R, S, far_n, nflag, acc);
     near_pass_mc<BLOCK>(R, S, near_n, total, acc);
-    __syncthreads();
-    if (S.ovl_t >= 0 && S.n_ovl > 0 && S.err == 0) overlap_below_far<2, BLOCK>(R, S, cnt2);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const double sum = wave_sum(acc[k]);
         if (lane == 0) S.red[w][k] = sum;
     }
     __syncthreads();
-    if (tid < 2) {
+    if (S.ovl_t >= 0 && S.n_ovl > 0 && S.err == 0) overlap_below_far<2, BLOCK>(R, S, cnt2);
+    // every thread sums the wave sums itself, in the same order
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
         double sum = 0.0;
-        for (int ww = 0; ww < NW; ++ww) sum += S.red[ww][tid];
-        S.res[tid] = sum;
+        for (int ww = 0; ww < NW; ++ww) sum += S.red[ww][k];
+        res[k] = sum;
     }
-    __syncthreads();
     return level;
 }
 
@@ -1052,7 +1054,8 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
             MS.nx_mo = imgs ? R.src[R.n + inext] : make_double4(0, 0, 0, 0);
         }
     };
-    const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook, MS.fs0, MS.level0);
+    double pot[2];
+    const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook, MS.fs0, MS.level0, pot);
     (void)levels;
     if (S.err) { out.stop = S.err == kErrStack ? -7 : -8; out.detail = S.err; __syncthreads(); return out; }
     if (th >= 0 && th < nps) {
@@ -1083,7 +1086,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         MS.list_mask[slot] = mask;
         MS.list_geo[slot] = MS.path_geo[j][l];
     }
-    const double po = S.res[0], pn = S.res[1];
+    const double po = pot[0], pn = pot[1];
     if (S.overlap || S.coincide) { out.reason = 2; __syncthreads(); return out; }
     // the move's positions and alpha come back from LDS: no registers held across the traversal
     const double4 so = MS.contrib[0], sn = MS.contrib[1];
