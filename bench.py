@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
 # counters on a plain 256 MiB device copy), valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "csrc": "e7f01ef4c00c",
-    "chain": {"moves": 100000, "bytes": 346051915, "l2_hit_rate": 0.9975},
-    "sweep": {"moves": 3038540, "bytes": 304110693949, "l2_hit_rate": 0.5863},
+    "csrc": "b76bf93c1a75",
+    "chain": {"moves": 100000, "bytes": 345892122, "l2_hit_rate": 0.9975},
+    "sweep": {"moves": 3038540, "bytes": 302847070724, "l2_hit_rate": 0.5857},
 }
 
 
