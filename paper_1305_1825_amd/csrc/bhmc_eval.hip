@@ -221,6 +221,7 @@ struct Trav {
     double4 es_i[NTG], es_k[NTG];
     uint32_t ovl[OVLCAP];
     int n_ovl, ovl_t, ovl_ex;
+    int near_tot;                    // slot total of the near leaves, from a one-wave scan
     int err, overlap, coincide;
     uint64_t wcnt[2][NW];            // per-wave packed list counts, double buffered
     uint64_t wsum[NW + 1];
@@ -262,9 +263,27 @@ __device__ __forceinline__ void far_pass(const Rep& R, Trav<NTG, BLOCK>& S, int 
     }
 }
 
-// Exclusive scan of the near leaves' slot counts (in place in near_pre).
+// Exclusive scan of the near leaves' slot counts (in place in near_pre).  Up to
+// 64 leaves (the usual case) the first wave scans them by shuffles and one
+// barrier publishes the result; beyond that, block scans of BLOCK at a time.
 template <int NTG, int BLOCK>
 __device__ int near_scan(Trav<NTG, BLOCK>& S, int near_n) {
+    if (near_n <= 64) {  // uniform
+        if (threadIdx.x < 64) {
+            const int j = threadIdx.x;
+            const int v = j < near_n ? S.near_pre[j] : 0;
+            int x = v;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(x, off, 64);
+                if (j >= off) x += y;
+            }
+            if (j < near_n) S.near_pre[j] = x - v;
+            if (j == 63) S.near_tot = x;
+        }
+        __syncthreads();
+        return S.near_tot;
+    }
     int carry = 0;
     for (int base = 0; base < near_n; base += BLOCK) {
         const int j = base + threadIdx.x;
