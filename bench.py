@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
 # counters on a plain 256 MiB device copy), valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "csrc": "b76bf93c1a75",
-    "chain": {"moves": 100000, "bytes": 345892122, "l2_hit_rate": 0.9975},
-    "sweep": {"moves": 3038540, "bytes": 302847070724, "l2_hit_rate": 0.5857},
+    "csrc": "514d07ed2ddd",
+    "chain": {"moves": 100000, "bytes": 345678524, "l2_hit_rate": 0.9975},
+    "sweep": {"moves": 3038540, "bytes": 306238197069, "l2_hit_rate": 0.5804},
 }
 
 
