@@ -990,44 +990,54 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     const bool imgs = R.images != 0;
     const int nps = imgs ? 4 : 2;
     if (outside(R, rx, ry, rz)) { out.reason = 1; return out; }
-    if (tid == 0) {
-        const double4 sn = make_double4(rx, ry, rz, si.w);
-        const double4 mn = imgs ? kelvin(R, rx, ry, rz, si.w) : make_double4(0, 0, 0, 0);
-        const uint64_t kio = morton_key(R, si.x, si.y, si.z);
-        const uint64_t kmo = imgs ? morton_key(R, mo.x, mo.y, mo.z) : 0;
-        S.tx[0] = si.x; S.ty[0] = si.y; S.tz[0] = si.z;
-        S.tx[1] = rx; S.ty[1] = ry; S.tz[1] = rz;
-        for (int t = 0; t < 2; ++t) {
-            S.ex_i[t] = i; S.ex_k[t] = imgs ? R.n + i : -1;
-            S.kx_i[t] = kio; S.kx_k[t] = kmo;
-            S.es_i[t] = si; S.es_k[t] = mo;
+    if (tid < 4) {
+        // lane j sets up contribution j (old ion, new ion, old image, new image) and its key,
+        // the four side by side; lane 0 then writes the targets' state
+        const int j = tid;
+        double4 cj;
+        if (j == 0) cj = si;
+        else if (j == 1) cj = make_double4(rx, ry, rz, si.w);
+        else if (j == 2) cj = mo;
+        else cj = imgs ? kelvin(R, rx, ry, rz, si.w) : make_double4(0, 0, 0, 0);
+        const uint64_t kj = (j < 2 || imgs) ? morton_key(R, cj.x, cj.y, cj.z) : 0;
+        MS.key[j] = kj;
+        MS.contrib[j] = cj;
+        const uint32_t klo = (uint32_t)kj, khi = (uint32_t)(kj >> 32);
+        const uint64_t kio = (uint64_t)(uint32_t)__shfl((int)klo, 0, 64) |
+                             ((uint64_t)(uint32_t)__shfl((int)khi, 0, 64) << 32);
+        const uint64_t kmo = (uint64_t)(uint32_t)__shfl((int)klo, 2, 64) |
+                             ((uint64_t)(uint32_t)__shfl((int)khi, 2, 64) << 32);
+        if (j == 0) {
+            S.tx[0] = si.x; S.ty[0] = si.y; S.tz[0] = si.z;
+            S.tx[1] = rx; S.ty[1] = ry; S.tz[1] = rz;
+            for (int t = 0; t < 2; ++t) {
+                S.ex_i[t] = i; S.ex_k[t] = imgs ? R.n + i : -1;
+                S.kx_i[t] = kio; S.kx_k[t] = kmo;
+                S.es_i[t] = si; S.es_k[t] = mo;
+            }
+            S.ovl_t = 1; S.ovl_ex = i; S.n_ovl = 0;
+            S.err = 0; S.overlap = 0; S.coincide = 0;
+            // The root holds both targets, so the MAC never takes it (theta < 1): it is opened
+            // for both whenever it is split and holds more than N_0 sources besides the two
+            // excluded ones.  Then the traversal starts from its children, cells 1..8 in digit
+            // order.
+            const int np_root = R.nsrc - 1 - (imgs ? 1 : 0);
+            if (R.ncell > 1 && np_root > R.n0) {
+                const int di = key_digit(kio, 1), dk = imgs ? key_digit(kmo, 1) : -1;
+                for (int d = 0; d < 8; ++d)
+                    S.front[0][d] = (uint32_t)(1 + d) | (3u << kMaskSh) | (d == di ? kFlagIon : 0u) |
+                                    (d == dk ? kFlagImg : 0u);
+                MS.fs0 = 8;
+                MS.level0 = 1;
+            } else {
+                S.front[0][0] = (3u << kMaskSh) | kFlagIon | (imgs ? kFlagImg : 0u);
+                MS.fs0 = 1;
+                MS.level0 = 0;
+            }
+            MS.alpha = alpha;
+            MS.err = 0;
+            MS.nlist = 0;
         }
-        S.ovl_t = 1; S.ovl_ex = i; S.n_ovl = 0;
-        S.err = 0; S.overlap = 0; S.coincide = 0;
-        // The root holds both targets, so the MAC never takes it (theta < 1): it is opened for
-        // both whenever it is split and holds more than N_0 sources besides the two excluded
-        // ones.  Then the traversal starts from its children, cells 1..8 in digit order.
-        const int np_root = R.nsrc - 1 - (imgs ? 1 : 0);
-        if (R.ncell > 1 && np_root > R.n0) {
-            const int di = key_digit(kio, 1), dk = imgs ? key_digit(kmo, 1) : -1;
-            for (int d = 0; d < 8; ++d)
-                S.front[0][d] = (uint32_t)(1 + d) | (3u << kMaskSh) | (d == di ? kFlagIon : 0u) |
-                                (d == dk ? kFlagImg : 0u);
-            MS.fs0 = 8;
-            MS.level0 = 1;
-        } else {
-            S.front[0][0] = (3u << kMaskSh) | kFlagIon | (imgs ? kFlagImg : 0u);
-            MS.fs0 = 1;
-            MS.level0 = 0;
-        }
-        MS.key[0] = kio;
-        MS.key[1] = morton_key(R, rx, ry, rz);
-        MS.key[2] = kmo;
-        MS.key[3] = imgs ? morton_key(R, mn.x, mn.y, mn.z) : 0;
-        MS.contrib[0] = si; MS.contrib[1] = sn; MS.contrib[2] = mo; MS.contrib[3] = mn;
-        MS.alpha = alpha;
-        MS.err = 0;
-        MS.nlist = 0;
     }
     // work beside the traversal runs on the last waves, which have no frontier entries to
     // classify on most levels, each task on a wave of its own (divergent lanes of one wave
