@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
 # counters on a plain 256 MiB device copy), valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "csrc": "514d07ed2ddd",
-    "chain": {"moves": 100000, "bytes": 345678524, "l2_hit_rate": 0.9975},
-    "sweep": {"moves": 3038540, "bytes": 306238197069, "l2_hit_rate": 0.5804},
+    "csrc": "1088f3503da1",
+    "chain": {"moves": 100000, "bytes": 347409521, "l2_hit_rate": 0.9976},
+    "sweep": {"moves": 3038540, "bytes": 309544652395, "l2_hit_rate": 0.5802},
 }
 
 
