@@ -1132,7 +1132,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     if (mode == 1) acc = dE <= 0.0 || MS.alpha <= exp(-dE);
     else if (mode == 2) acc = true;
     if (!acc) { __syncthreads(); return out; }
-    if (tid == 0) {
+    if (tid == BLOCK - 1) {  // a thread with no path-cell item above
         // the tracked leaves must be the leaves the old positions' keys lead to,
         // and the tracked slots must hold the movers
         bool sane = MS.tr[0].x == MS.path[0][MS.plen[0] - 1] && MS.self_pidx[0] == i;
