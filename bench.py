@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
 # counters on a plain 256 MiB device copy), valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "csrc": "1088f3503da1",
-    "chain": {"moves": 100000, "bytes": 347409521, "l2_hit_rate": 0.9976},
-    "sweep": {"moves": 3038540, "bytes": 309544652395, "l2_hit_rate": 0.5802},
+    "csrc": "39c0901e87ab",
+    "chain": {"moves": 100000, "bytes": 347086782, "l2_hit_rate": 0.9976},
+    "sweep": {"moves": 3038540, "bytes": 307839059374, "l2_hit_rate": 0.5779},
 }
 
 
