@@ -78,6 +78,7 @@ def _declare(L):
         "orc_tree_build": (C.c_int, [_P, C.c_int64, _d, _d, _d, _d, C.POINTER(_T)]),
         "orc_tree_free": (None, [_T]),
         "orc_tree_phi": (C.c_double, [_T, _d, C.POINTER(C.c_int), C.c_int]),
+        "orc_tree_phi_counts": (C.c_double, [_T, _d, C.POINTER(C.c_int), C.c_int, _i64]),
         "orc_tree_delta": (C.c_double, [_T, C.c_int64, _d, C.POINTER(C.c_int), _i64]),
         "orc_tree_commit": (C.c_int, [_T, C.c_int64, _d]),
         "orc_tree_energy": (C.c_double, [_T, _d]),
@@ -305,6 +306,14 @@ class Tree:
         r = _f64(xt)
         ex = (C.c_int * max(len(exclude), 1))(*[int(e) for e in exclude])
         return lib().orc_tree_phi(self.h, _ptr(r, _d), ex, len(exclude))
+
+    def phi_counts(self, xt, exclude=()):
+        """Potential and the traversal's counts (visited, far, near sources) for one target."""
+        r = _f64(xt)
+        ex = (C.c_int * max(len(exclude), 1))(*[int(e) for e in exclude])
+        c = np.zeros(3, dtype=np.int64)
+        v = lib().orc_tree_phi_counts(self.h, _ptr(r, _d), ex, len(exclude), _ptr(c, _i64))
+        return v, c
 
     def certificate(self, xt, exclude=()):
         r = _f64(xt)

@@ -519,6 +519,9 @@ static int validate(const orc_params *P, int64_t n, const double *x, const doubl
         !(P->box_side > 0.0) || P->n0 < 0)
         return ORC_EINVAL;
     if (P->images && P->geom != 1) return ORC_EINVAL;
+    if (P->geom == 1) /* the root cube must contain the shell |r| < r_max */
+        for (int d = 0; d < 3; ++d)
+            if (!(P->box_lo[d] <= -P->r_max && P->box_lo[d] + P->box_side >= P->r_max)) return ORC_EINVAL;
     for (int64_t i = 0; i < n; ++i) {
         if (!(isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]))) return ORC_EINVAL;
         if (outside(P, x[i], y[i], z[i]) || !in_root(P, x[i], y[i], z[i])) return ORC_EOUTSIDE;
@@ -678,6 +681,16 @@ static double tree_phi(otree *t, const double *xt, const int *ex, int nex, int *
 
 double orc_tree_phi(otree *t, const double *xt, const int *ex, int nex) {
     return tree_phi(t, xt, ex, nex, NULL);
+}
+
+/* The same potential with the traversal's counts of that one target:
+ * counts = [cells visited (holding a remaining source), cells taken as far,
+ * sources summed directly]. */
+double orc_tree_phi_counts(otree *t, const double *xt, const int *ex, int nex, int64_t *counts) {
+    memset(&t->cnt, 0, sizeof(t->cnt));
+    double v = tree_phi(t, xt, ex, nex, NULL);
+    counts[0] = t->cnt.visited; counts[1] = t->cnt.far; counts[2] = t->cnt.near_src;
+    return v;
 }
 
 static int overlaps(const otree *t, int64_t i, const double *rn) {
