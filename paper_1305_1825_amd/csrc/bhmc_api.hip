@@ -151,11 +151,18 @@ static bhmc_status check_params(const bhmc_params& P, int64_t n) {
     if (P.p < 0 || P.p > bhmc::kPMax) return fail(BHMC_EINVAL, "p must lie in [0, %d]", bhmc::kPMax);
     if (P.leaf_cap < 0 || P.n0 < 0) return fail(BHMC_EINVAL, "leaf_cap and n0 must be >= 0");
     if (P.max_depth < 0 || P.max_depth > bhmc::kMaxDepth) return fail(BHMC_EINVAL, "max_depth must lie in [0, 21]");
-    if (P.slot_slack < 1) return fail(BHMC_EINVAL, "slot_slack must be >= 1");
+    if (P.slot_slack < 1 || P.slot_slack > 1024) return fail(BHMC_EINVAL, "slot_slack must lie in [1, 1024]");
+    if (P.leaf_cap > (1 << 23)) return fail(BHMC_EINVAL, "leaf_cap must be <= 2^23");
     if (!(P.box_side > 0.0) || !std::isfinite(P.box_side)) return fail(BHMC_EINVAL, "box_side must be > 0");
     if (P.geom != 0 && P.geom != 1) return fail(BHMC_EINVAL, "geom must be 0 or 1");
     if (P.images && P.geom != 1) return fail(BHMC_EINVAL, "images need the spherical geometry");
     if (P.geom == 1 && !(P.r_min >= 0.0 && P.r_min < P.r_max)) return fail(BHMC_EINVAL, "need 0 <= r_min < r_max");
+    if (P.geom == 1) {
+        // every point of the shell (|r| < r_max) must lie in the root cube [lo, lo + side)^3
+        for (int d = 0; d < 3; ++d)
+            if (!(P.box_lo[d] <= -P.r_max && P.box_lo[d] + P.box_side >= P.r_max))
+                return fail(BHMC_EINVAL, "the root cube must contain the shell |r| < r_max");
+    }
     if (P.images && !(P.a > 0.0 && P.a <= P.r_min && P.eps_in > 0.0 && P.eps_out >= 0.0))
         return fail(BHMC_EINVAL, "images need 0 < a <= r_min and eps_in > 0");
     if (!(P.hard_core >= 0.0) || !(P.l_B >= 0.0)) return fail(BHMC_EINVAL, "hard_core and l_B must be >= 0");
@@ -314,6 +321,9 @@ static bhmc_status build_list(bhmc_tree* t, const std::vector<int>& list, const 
     if ((st = download(t))) return st;
     for (int r : list) {
         Rep& h = t->host[r];
+        if (h.status == -4)
+            return fail(BHMC_EINVAL, "replica %d: leaf index arrays of slot_slack * (sources + leaves * leaf_cap) "
+                        "slots exceed 2^31", r);
         if (h.status) return fail(h.status == -1 ? BHMC_EINVAL : BHMC_EOUTSIDE, "replica %d: %s", r, status_name(h.status));
         if (h.ncell >= (1 << 24)) return fail(BHMC_EINVAL, "replica %d: %d cells exceed 2^24", r, h.ncell);
     }

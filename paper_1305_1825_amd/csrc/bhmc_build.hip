@@ -177,8 +177,15 @@ k_count(Rep* reps, const int* rep_list) {
         R.ncell = 1 + 8 * total;
         R.nleaf = R.ncell - total;
         R.depth = depth;
-        // sum_leaves max(count, cap) <= nsrc + nleaf * leaf_cap
-        R.pool = R.slack * (R.nsrc + R.nleaf * R.leaf_cap) + 2 * R.nleaf;
+        // sum_leaves max(count, cap) <= nsrc + nleaf * leaf_cap; every slot index must fit an int
+        const long long pool = (long long)R.slack * ((long long)R.nsrc + (long long)R.nleaf * R.leaf_cap) +
+                               2ll * R.nleaf;
+        if (pool > 0x7FFFFFFFll - 64) {
+            R.pool = 0;
+            R.status = -4;
+        } else {
+            R.pool = (int)pool;
+        }
     }
 }
 

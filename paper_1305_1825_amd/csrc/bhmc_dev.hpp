@@ -107,10 +107,14 @@ __device__ __forceinline__ Draw draw_move(uint64_t seed, uint32_t replica, uint6
 }
 
 // ------------------------------------------------------------ keys
+// k = min(2^21 - 1, floor((v - lo) scale)), clamped in floating point before the
+// conversion so that it is defined for every input (a position outside the root
+// cube maps to the nearest face cell).
 __device__ __forceinline__ uint32_t quantize(double v, double lo, double scale) {
     double f = floor((v - lo) * scale);
-    uint32_t k = (uint32_t)f;
-    return k > 2097151u ? 2097151u : k;
+    f = f >= 0.0 ? f : 0.0;
+    f = f <= 2097151.0 ? f : 2097151.0;
+    return (uint32_t)f;
 }
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {

@@ -97,9 +97,10 @@ def shell_system(charges: np.ndarray, r_min: float, r_max: float, hard_core: flo
 
 
 def shell_params(a, Q_center, r_min, r_max, **kw):
-    return make_params(geom=1, images=1, a=a, Q_center=Q_center, eps_in=2.0, eps_out=80.0,
-                       r_min=r_min, r_max=r_max, box_lo=(-r_max, -r_max, -r_max),
-                       box_side=2.0 * r_max, **kw)
+    base = dict(geom=1, images=1, a=a, Q_center=Q_center, eps_in=2.0, eps_out=80.0,
+                r_min=r_min, r_max=r_max, box_lo=(-r_max, -r_max, -r_max), box_side=2.0 * r_max)
+    base.update(kw)
+    return make_params(**base)
 
 
 # ---------------------------------------------------------------- configurations

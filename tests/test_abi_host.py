@@ -30,7 +30,11 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("bad", [dict(theta=1.0), dict(theta=-0.1), dict(p=11), dict(p=-1),
                                  dict(max_depth=22), dict(slot_slack=0), dict(box_side=0.0),
-                                 dict(images=1), dict(geom=2), dict(leaf_cap=-1)])
+                                 dict(images=1), dict(geom=2), dict(leaf_cap=-1), dict(slot_slack=1025),
+                                 dict(leaf_cap=(1 << 23) + 1),
+                                 # shell configurations whose root cube misses part of the shell
+                                 W.shell_params(10.0, 0.0, 10.5, 40.0, box_side=79.0),
+                                 W.shell_params(10.0, 0.0, 10.5, 40.0, box_lo=(-40.0, -39.0, -40.0))])
 def test_parameter_validation_on_host(bad):
     P = W.make_params(**bad)
     pp = bhmc.make_params(P)
