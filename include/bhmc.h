@@ -45,7 +45,7 @@ typedef enum {
     BHMC_ENOMEM = -4,     /* device allocation failed                         */
     BHMC_EHIP = -5,       /* a HIP runtime call failed                        */
     BHMC_ECAPACITY = -6,  /* a leaf's index array is full (see bhmc_commit_move) */
-    BHMC_ESTACK = -7,     /* a traversal list outgrew its on-chip capacity    */
+    BHMC_ESTACK = -7,     /* a traversal list outgrew its capacity (see bhmc_set_frontier_capacity) */
     BHMC_EINTERNAL = -8   /* a device-side index check failed; the handle must be freed */
 } bhmc_status;
 
@@ -236,9 +236,27 @@ bhmc_status bhmc_set_launch_shape(bhmc_tree* tree, int32_t shape);
 bhmc_status bhmc_energy_grad(bhmc_tree* tree, int32_t replica, double* dEdr_dev, double* dEdq_dev,
                              double* E_host);
 
+/* Frontier capacity of the breadth-first MAC traversals (Sec. 3.2).  A level
+ * keeps up to lds_entries frontier entries on chip (64..4096; 4096 after
+ * build).  With allow_spill = 1 (the default) a level that outgrows them
+ * continues in HBM regions the library allocates the first time this happens
+ * (per handle, 8 B per cell of the largest replica per workgroup region, one
+ * region per workgroup of a launch), and the call that stopped runs again; a
+ * traversal then never fails for lack of frontier space, so theta = 0 (the
+ * direct sum) works at any size.  With allow_spill = 0 such a call returns
+ * BHMC_ESTACK instead.  The results do not depend on where the frontier lives. */
+bhmc_status bhmc_set_frontier_capacity(bhmc_tree* tree, int32_t lds_entries, int32_t allow_spill);
+
 /* Current ion positions and charges of a replica (dev outputs, n each). */
 bhmc_status bhmc_get_state(bhmc_tree* tree, int32_t replica, double* x, double* y, double* z,
                            double* q);
+
+/* Recompute a replica's moments (eq. 3.3) from the current members of its
+ * leaves, on the tree as it stands (no change of cells or leaf index
+ * arrays): P2M at the leaves, then M2M up the tree.  Accepted moves repair the
+ * moments incrementally (Sec. 3.3); this replaces them by a fresh sum, which
+ * differs from the repaired one only by rounding. */
+bhmc_status bhmc_refresh_moments(bhmc_tree* tree, int32_t replica);
 
 /* Rebuild a replica's tree from its current positions. */
 bhmc_status bhmc_rebuild(bhmc_tree* tree, int32_t replica);

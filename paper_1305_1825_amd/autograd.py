@@ -1,10 +1,11 @@
 """The treecode energy as a differentiable torch function.
 
-Forward builds an octree from the given positions and charges (so every
-moment is computed fresh from them), evaluates the treecode energy of Sec. 3
-and, in the same library call, its exact gradient for the interaction lists
-the traversal makes (dE/dr per ion, and dE/dq).  Backward only scales that
-gradient.  All the work runs in the HIP library; this module marshals tensors.
+Forward builds an octree from the given positions and charges and evaluates
+the treecode energy of Sec. 3; it keeps nothing of the tree.  Backward builds
+the tree again from the saved positions and charges (every moment recomputed,
+none stored between the passes) and evaluates the exact gradient of that same
+energy for the interaction lists its traversal makes (dE/dr per ion, and
+dE/dq).  All the work runs in the HIP library; this module marshals tensors.
 """
 from __future__ import annotations
 
@@ -18,15 +19,21 @@ class TreecodeEnergy(torch.autograd.Function):
     def forward(ctx, x, y, z, q, params):
         tree = bhmc.Tree(params, x.detach(), y.detach(), z.detach(), q.detach(), device=x.device)
         try:
-            E, g, gq = tree.energy_grad()
+            E = tree.energy()
         finally:
             tree.close()
-        ctx.save_for_backward(g, gq)
+        ctx.params = dict(params)
+        ctx.save_for_backward(x.detach(), y.detach(), z.detach(), q.detach())
         return torch.tensor(E, dtype=torch.float64, device=x.device)
 
     @staticmethod
     def backward(ctx, grad_out):
-        g, gq = ctx.saved_tensors
+        x, y, z, q = ctx.saved_tensors
+        tree = bhmc.Tree(ctx.params, x, y, z, q, device=x.device)
+        try:
+            _, g, gq = tree.energy_grad()
+        finally:
+            tree.close()
         return grad_out * g[:, 0], grad_out * g[:, 1], grad_out * g[:, 2], grad_out * gq, None
 
 

@@ -73,8 +73,10 @@ SIGNATURES = {
     "bhmc_batch_autotune": [_v, C.c_uint64, C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)],
     "bhmc_set_launch_shape": [_v, C.c_int32],
     "bhmc_energy_grad": [_v, C.c_int32, _v, _v, _d],
+    "bhmc_set_frontier_capacity": [_v, C.c_int32, C.c_int32],
     "bhmc_get_state": [_v, C.c_int32, _v, _v, _v, _v],
     "bhmc_rebuild": [_v, C.c_int32],
+    "bhmc_refresh_moments": [_v, C.c_int32],
     "bhmc_get_sorted": [_v, C.c_int32, _u64, _i32],
     "bhmc_get_cells": [_v, C.c_int32, _i32, _u64, _i32, _i32, _d, _d],
     "bhmc_get_leaves": [_v, C.c_int32, _i32, _i32, _i32, _i32, _i32],
@@ -246,12 +248,19 @@ class Tree:
         _check(lib().bhmc_energy_grad(self.h, replica, g.data_ptr(), gq.data_ptr(), C.byref(E)), "energy_grad")
         return E.value, g, gq
 
+    def set_frontier_capacity(self, lds_entries=4096, allow_spill=True):
+        _check(lib().bhmc_set_frontier_capacity(self.h, int(lds_entries), 1 if allow_spill else 0),
+               "set_frontier_capacity")
+
     def state(self, replica=0):
         torch = _torch()
         n = self.n_per[replica]
         out = [torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(4)]
         _check(lib().bhmc_get_state(self.h, replica, *[t.data_ptr() for t in out]), "get_state")
         return out
+
+    def refresh_moments(self, replica=0):
+        _check(lib().bhmc_refresh_moments(self.h, replica), "refresh_moments")
 
     def rebuild(self, replica=0):
         _check(lib().bhmc_rebuild(self.h, replica), "rebuild")

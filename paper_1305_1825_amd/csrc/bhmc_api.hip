@@ -114,6 +114,13 @@ struct bhmc_tree {
     double* eterm = nullptr; int eterm_n = 0;
     char* gwork = nullptr; size_t gwork_bytes = 0;  // gradient workspace
     double* scalar = nullptr;
+    // HBM frontier regions, allocated the first time a traversal level outgrows its LDS capacity
+    uint32_t* spill = nullptr;
+    int spill_regions = 0;
+    long long spill_words = 0;       // 32-bit words per region
+    int fcap = 4096;                 // frontier entries a level keeps in LDS
+    int allow_spill = 1;
+    bool energy_bounded = false;     // energy / gradient launches keep their grid within the regions
     int mc_grid = 1;
     int mc_wide = 1;                 // one replica: the 512-thread Metropolis kernel
     hipGraph_t graph = nullptr;
@@ -191,6 +198,7 @@ static void fill_rep(Rep& r, const bhmc_params& P, int64_t n) {
     r.max_depth = P.max_depth; r.slack = P.slot_slack;
     r.n = (int)n;
     r.nsrc = P.images ? 2 * (int)n : (int)n;
+    r.fcap = 4096;
 }
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -286,6 +294,44 @@ static bhmc_status download(bhmc_tree* t) {
     return BHMC_OK;
 }
 
+// Frontier regions in HBM for every workgroup that may need one: one per workgroup of the
+// Metropolis launch and of a bounded energy / gradient launch.  A region holds the two levels a
+// traversal keeps at once of its widest possible frontier: 4 targets x every cell (energy,
+// 32-bit entries), or every cell with a 32-bit cell and a 64-bit mask word (gradient).  Sized
+// for the replicas' current cell counts; returns whether it had to grow.
+static bhmc_status ensure_spill(bhmc_tree* t, bool* grown) {
+    *grown = false;
+    long long maxc = 1;
+    for (int r = 0; r < t->R; ++r) maxc = std::max<long long>(maxc, t->host[r].ncell);
+    const long long words = (8 * maxc + 16 + 63) & ~63ll;
+    int dev = 0, ncu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int regions = std::max(std::max(512, 2 * ncu), t->mc_grid);
+    if (t->spill && words <= t->spill_words && regions <= t->spill_regions) return BHMC_OK;
+    if (t->spill) { hipFree(t->spill); t->spill = nullptr; t->spill_words = 0; t->spill_regions = 0; }
+    HIP_TRY(hipMalloc(&t->spill, sizeof(uint32_t) * (size_t)words * regions));
+    t->spill_words = words;
+    t->spill_regions = regions;
+    for (int r = 0; r < t->R; ++r) {
+        t->host[r].spill = t->spill;
+        t->host[r].spill_words = words;
+        t->host[r].spill_regions = regions;
+    }
+    *grown = true;
+    return BHMC_OK;
+}
+
+// After a traversal stopped with detail `detail`: true if it stopped because a level outgrew
+// the LDS frontier and HBM regions (now allocated or grown) let it run again.
+static bool retry_with_spill(bhmc_tree* t, int detail, bhmc_status* st) {
+    *st = BHMC_OK;
+    if (detail != bhmc::kErrFrontier || !t->allow_spill) return false;
+    bool grown = false;
+    if ((*st = ensure_spill(t, &grown))) return false;
+    return grown;
+}
+
 static const char* status_name(int s) {
     switch (s) {
         case -1: return "a non-finite coordinate or charge";
@@ -352,6 +398,7 @@ static void destroy(bhmc_tree* t) {
     for (void* p : t->arena2) if (p) hipFree(p);
     hipFree(t->reps); hipFree(t->queue); hipFree(t->list_all); hipFree(t->list_one); hipFree(t->list_rest);
     hipFree(t->sweep_add); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar); hipFree(t->gwork);
+    hipFree(t->spill);
     if (t->host) hipHostFree(t->host);
     if (t->pin) hipHostFree(t->pin);
     delete t;
@@ -462,6 +509,16 @@ static bhmc_status rebuild_one(bhmc_tree* t, int r) {
     return build_list(t, list, nullptr, nullptr, nullptr, nullptr, {});
 }
 
+extern "C" bhmc_status bhmc_refresh_moments(bhmc_tree* t, int32_t replica) {
+    bhmc_status st = check_rep(t, replica);
+    if (st) return st;
+    if ((st = h2d(t, t->list_one, &replica, sizeof(int)))) return st;
+    bhmc::launch_moments(t->stream, 1, t->reps, t->list_one, t->nterms, t->mstride, t->host, &replica);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    return BHMC_OK;
+}
+
 extern "C" bhmc_status bhmc_rebuild(bhmc_tree* tree, int32_t replica) {
     bhmc_status st = check_rep(tree, replica);
     if (st) return st;
@@ -479,8 +536,10 @@ static bhmc_status ensure_eterm(bhmc_tree* t, int n) {
     return BHMC_OK;
 }
 
-// Sum of the per-ion energy terms; a NaN there marks a failed traversal.
-static bhmc_status finish_energy(bhmc_tree* t, int r, int n, double* E_host, const char* what) {
+// Sum of the per-ion energy terms; a NaN there marks a failed traversal.  *again: the
+// traversal ran out of LDS frontier and should run again with HBM regions (now allocated).
+static bhmc_status finish_energy(bhmc_tree* t, int r, int n, double* E_host, const char* what, bool* again) {
+    *again = false;
     bhmc::launch_sum(t->stream, t->eterm, n, t->host[r].l_B, t->scalar);
     HIP_TRY(hipGetLastError());
     double E = 0.0;
@@ -489,21 +548,35 @@ static bhmc_status finish_energy(bhmc_tree* t, int r, int n, double* E_host, con
     if (std::isnan(E)) {
         if ((st = download(t))) return st;
         const int d = t->host[r].err_detail;
-        if (d > 1) return fail(BHMC_EINTERNAL, "device index check %d failed in the %s traversal", d, what);
-        return fail(BHMC_ESTACK, "a traversal list outgrew its LDS capacity");
+        if (retry_with_spill(t, d, &st) || (d == bhmc::kErrFrontier && t->spill && !t->energy_bounded)) {
+            t->host[r].err_detail = 0;
+            t->energy_bounded = true;
+            if ((st = upload(t))) return st;
+            *again = true;
+            return BHMC_OK;
+        }
+        if (st) return st;
+        if (d > 1 && d != bhmc::kErrFrontier)
+            return fail(BHMC_EINTERNAL, "device index check %d failed in the %s traversal", d, what);
+        return fail(BHMC_ESTACK, "a traversal list outgrew its capacity");
     }
     if (E_host) *E_host = E;
     return BHMC_OK;
 }
+
+static int energy_grid_bound(const bhmc_tree* t) { return t->energy_bounded && t->spill ? t->spill_regions : 0; }
 
 extern "C" bhmc_status bhmc_energy(bhmc_tree* t, int32_t replica, double* E_host, double* phi_dev) {
     bhmc_status st = check_rep(t, replica);
     if (st) return st;
     const int n = t->host[replica].n;
     if ((st = ensure_eterm(t, n))) return st;
-    t->ops->energy(t->stream, t->reps, replica, n, phi_dev, t->eterm);
-    HIP_TRY(hipGetLastError());
-    return finish_energy(t, replica, n, E_host, "energy");
+    for (;;) {
+        t->ops->energy(t->stream, t->reps, replica, n, phi_dev, t->eterm, energy_grid_bound(t));
+        HIP_TRY(hipGetLastError());
+        bool again = false;
+        if ((st = finish_energy(t, replica, n, E_host, "energy", &again)) || !again) return st;
+    }
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -537,9 +610,12 @@ extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* d
     w.rank = (int*)(t->gwork + lb + gb + tb);
     w.islot = (int*)(t->gwork + lb + gb + tb + ob);
     w.ncell = h.ncell; w.nleaf = h.nleaf; w.nsrc = h.nsrc; w.n = n;
-    t->ops->grad(t->stream, t->reps, replica, w, dEdr_dev, dEdq_dev, t->eterm);
-    HIP_TRY(hipGetLastError());
-    return finish_energy(t, replica, n, E_host, "gradient");
+    for (;;) {
+        t->ops->grad(t->stream, t->reps, replica, w, dEdr_dev, dEdq_dev, t->eterm, energy_grid_bound(t));
+        HIP_TRY(hipGetLastError());
+        bool again = false;
+        if ((st = finish_energy(t, replica, n, E_host, "gradient", &again)) || !again) return st;
+    }
 }
 
 static bhmc_status run_move(bhmc_tree* t, int64_t i, const double* r_new, int mode, bhmc::MoveIO& io) {
@@ -552,11 +628,23 @@ static bhmc_status run_move(bhmc_tree* t, int64_t i, const double* r_new, int mo
     io.i = (int)i;
     io.rn[0] = r_new[0]; io.rn[1] = r_new[1]; io.rn[2] = r_new[2];
     io.mode = mode;
-    if ((st = h2d(t, t->io, &io, sizeof(io)))) return st;
-    t->ops->move(t->stream, t->reps, 0, t->io);
-    HIP_TRY(hipGetLastError());
-    if ((st = d2h(t, &io, t->io, sizeof(io)))) return st;
-    if (io.status == -7) return fail(BHMC_ESTACK, "a traversal list outgrew its LDS capacity");
+    const bhmc::MoveIO io_in = io;
+    for (;;) {
+        io = io_in;
+        if ((st = h2d(t, t->io, &io, sizeof(io)))) return st;
+        t->ops->move(t->stream, t->reps, 0, t->io);
+        HIP_TRY(hipGetLastError());
+        if ((st = d2h(t, &io, t->io, sizeof(io)))) return st;
+        if (io.status != -7) break;
+        if ((st = download(t))) return st;
+        if (retry_with_spill(t, t->host[0].err_detail, &st)) {
+            t->host[0].err_detail = 0;
+            if ((st = upload(t))) return st;
+            continue;
+        }
+        if (st) return st;
+        return fail(BHMC_ESTACK, "a traversal list outgrew its capacity");
+    }
     if (io.status == -8) {
         bhmc_status s2 = download(t);
         if (s2) return s2;
@@ -599,7 +687,17 @@ static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArg
         bhmc_status st = download(t);
         if (st) return st;
         const Rep& h = t->host[r];
-        if (h.mc_status == -7) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its LDS capacity", r);
+        if (h.mc_status == -7) {
+            if (retry_with_spill(t, h.err_detail, &st)) {
+                // nothing of the stopped move was committed: run it again with HBM frontier regions
+                t->host[r].mc_status = 0;
+                t->host[r].err_detail = 0;
+                if ((st = upload(t))) return st;
+                continue;
+            }
+            if (st) return st;
+            return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its capacity", r);
+        }
         if (h.mc_status == -8)
             return fail(BHMC_EINTERNAL, "replica %d: device index check %d failed at move %lld", r, h.err_detail, h.move_next);
         if (h.mc_status == -6) {
@@ -655,9 +753,19 @@ static bhmc_status finish_sweep(bhmc_tree* t, const bhmc::McArgs& base, std::vec
         bhmc_status st = download(t);
         if (st) return st;
         std::vector<int> stalled, rest;
+        bool respill = false;
         for (int r : t->order) {
-            const Rep& h = t->host[r];
-            if (h.mc_status == -7) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its LDS capacity", r);
+            Rep& h = t->host[r];
+            if (h.mc_status == -7) {
+                bool grown = false;
+                if (h.err_detail == bhmc::kErrFrontier && t->allow_spill && !respill) {
+                    if ((st = ensure_spill(t, &grown))) return st;
+                    respill = grown;
+                }
+                if (!respill) return fail(BHMC_ESTACK, "replica %d: a traversal list outgrew its capacity", r);
+                h.mc_status = 0;  // its stopped move runs again with HBM frontier regions
+                h.err_detail = 0;
+            }
             if (h.mc_status == -8)
                 return fail(BHMC_EINTERNAL, "replica %d: device index check %d failed at move %lld", r, h.err_detail,
                             h.move_next);
@@ -677,6 +785,7 @@ static bhmc_status finish_sweep(bhmc_tree* t, const bhmc::McArgs& base, std::vec
             for (int r : stalled) ++rebuilds[r];
         }
         for (int r : rest) t->host[r].mc_status = 0;
+        (void)respill;
         if ((st = upload(t))) return st;
         if ((st = h2d(t, t->list_rest, rest.data(), sizeof(int) * rest.size()))) return st;
         bhmc::McArgs a = base;
@@ -846,6 +955,17 @@ extern "C" bhmc_status bhmc_set_launch_shape(bhmc_tree* t, int32_t shape) {
     t->mc_grid = std::max(1, std::min(t->R, kShapes[shape].per_cu * ncu));
     t->graph_ok = false;
     return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_set_frontier_capacity(bhmc_tree* t, int32_t lds_entries, int32_t allow_spill) {
+    if (!t) return fail(BHMC_EINVAL, "null tree");
+    if (lds_entries < 64 || lds_entries > 4096) return fail(BHMC_EINVAL, "lds_entries must lie in [64, 4096]");
+    bhmc_status st = download(t);
+    if (st) return st;
+    t->fcap = lds_entries;
+    t->allow_spill = allow_spill ? 1 : 0;
+    for (int r = 0; r < t->R; ++r) t->host[r].fcap = lds_entries;
+    return upload(t);
 }
 
 extern "C" bhmc_status bhmc_get_state(bhmc_tree* t, int32_t r, double* x, double* y, double* z, double* q) {

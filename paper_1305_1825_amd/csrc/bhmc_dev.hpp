@@ -20,7 +20,8 @@ enum ErrDetail {
     kErrNone = 0, kErrStack = 1, kErrFrontCell = 2, kErrChildLink = 3, kErrFarCell = 4,
     kErrNearLeaf = 5, kErrNearSlots = 6, kErrOvlLeaf = 7, kErrPathCell = 8, kErrPathDepth = 9,
     kErrCommitLeaf = 10, kErrCommitSlot = 11, kErrCommitSource = 12, kErrFlagCell = 13,
-    kErrMomentCell = 14, kErrBuildPerm = 15, kErrBuildCell = 16, kErrBuildPool = 17
+    kErrMomentCell = 14, kErrBuildPerm = 15, kErrBuildCell = 16, kErrBuildPool = 17,
+    kErrFrontier = 18  // a level's frontier outgrew its LDS capacity and no HBM region could take it
 };
 
 // Per-replica descriptor.  Host writes parameters and pointers, kernels write
@@ -39,6 +40,12 @@ struct Rep {
     int ncell, nleaf, pool, depth, nsplit;
     int level_start[kMaxLevels + 1];
     int status;                    // build status (0 or a negative bhmc_status)
+    // ---- frontier spill (host): a level whose frontier outgrows fcap entries in LDS continues in
+    // the HBM region of its workgroup (blockIdx.x < spill_regions), spill_words 32-bit words each
+    int fcap;
+    int spill_regions;
+    long long spill_words;
+    uint32_t* spill;
     // ---- buffers
     double4* src;                  // (x, y, z, q) per source, home copy
     uint64_t* keys; int* perm;     // sorted keys and source index, as built

@@ -201,6 +201,13 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Frontier region of this workgroup in HBM (null if none): a level whose frontier
+// outgrows its LDS capacity continues there, and so do the levels after it.
+__device__ __forceinline__ uint32_t* spill_region(const Rep& R) {
+    return (R.spill && (int)blockIdx.x < R.spill_regions) ? R.spill + (size_t)blockIdx.x * (size_t)R.spill_words
+                                                          : nullptr;
+}
+
 template <int NTG, int BLOCK>
 struct Trav {
     static constexpr int FCAP = 4096;
@@ -400,7 +407,13 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
 #pragma unroll
     for (int k = 0; k < NTG; ++k) acc[k] = 0.0;
     int cur = 0, fs = nroot, far_n = 0, near_n = 0, nflag = 0, buf = 0;
-    bool failed = false;
+    bool failed = false, frontier_full = false;
+    // the frontier: front[] in LDS up to lcap entries, then the workgroup's HBM region (two halves
+    // of gcap entries); rg / wg: the level read / the level written is in HBM (uniform)
+    uint32_t* const gfr = spill_region(R);
+    const int gcap = gfr ? (int)(R.spill_words / 2 < 0x7FFFFFFF ? R.spill_words / 2 : 0x7FFFFFFF) : 0;
+    const int lcap = R.fcap < TS::FCAP ? R.fcap : TS::FCAP;
+    bool rg = false, wg = false;
     int level = 0;
     for (; fs > 0 && !failed; ++level) {
         int next_n = 0;
@@ -420,7 +433,7 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
             }
             const int j = base + tid;
             const bool valid = j < fs;
-            const uint32_t e = valid ? S.front[cur][j] : 0u;
+            const uint32_t e = valid ? (rg ? gfr[(size_t)cur * gcap + j] : S.front[cur][j]) : 0u;
             const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
             const int fi = (e & kFlagIon) ? 1 : 0, fk = (e & kFlagImg) ? 1 : 0;
             int kind = 0;
@@ -479,9 +492,18 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
             buf ^= 1;
             const int tf = (int)(tot & 0xffff), tn = (int)((tot >> 16) & 0xffff);
             const int ts = (int)((tot >> 32) & 0xffff), tg = (int)(tot >> 48);
-            if (next_n + 8 * ts > TS::FCAP || nflag + tg > 2 * NTG) {  // uniform
+            if (nflag + tg > 2 * NTG) {  // uniform
                 failed = true;
                 break;
+            }
+            if (next_n + 8 * ts > (wg ? gcap : lcap)) {  // uniform
+                if (wg || next_n + 8 * ts > gcap) {
+                    failed = frontier_full = true;
+                    break;
+                }
+                // the next level moves to HBM: what this level wrote so far first
+                for (int k = tid; k < next_n; k += BLOCK) gfr[(size_t)(cur ^ 1) * gcap + k] = S.front[cur ^ 1][k];
+                wg = true;
             }
             if (kind == 1) {
                 S.farl[far_n + (int)(before & 0xffff) + __popcll(bf & lt)] = e;
@@ -500,7 +522,8 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
                     const uint32_t fl = (d == dig_i ? kFlagIon : 0u) | (d == dig_k ? kFlagImg : 0u) | cdir;
-                    S.front[cur ^ 1][o + d] = pack(m.y + d, t, fl);
+                    if (wg) gfr[(size_t)(cur ^ 1) * gcap + o + d] = pack(m.y + d, t, fl);
+                    else S.front[cur ^ 1][o + d] = pack(m.y + d, t, fl);
                 }
             }
             far_n += tf; near_n += tn; nflag += tg; next_n += 8 * ts;
@@ -508,9 +531,10 @@ __device__ int traverse(const Rep& R, Trav<NTG, BLOCK>& S, int nroot, int* cnt2,
         __syncthreads();  // the next level reads what this one wrote
         cur ^= 1;
         fs = next_n;
+        rg = wg;
     }
     if (failed) {
-        if (tid == 0) S.err = kErrStack;
+        if (tid == 0) S.err = frontier_full ? kErrFrontier : kErrStack;
         __syncthreads();
         return level;
     }
@@ -627,7 +651,12 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
     double acc[2] = {0.0, 0.0};
     int cur = 0, fs = fs0, far_n = 0, near_n = 0, nflag = 0, buf = 0;
-    bool failed = false;
+    bool failed = false, frontier_full = false;
+    // the frontier: LDS up to lcap entries, then HBM (see traverse)
+    uint32_t* const gfr = spill_region(R);
+    const int gcap = gfr ? (int)(R.spill_words / 2 < 0x7FFFFFFF ? R.spill_words / 2 : 0x7FFFFFFF) : 0;
+    const int lcap = R.fcap < TS::FCAP ? R.fcap : TS::FCAP;
+    bool rg = false, wg = false;
     int level = level0;
     for (; fs > 0 && !failed; ++level) {
         int next_n = 0;
@@ -647,7 +676,7 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
             }
             const int j = base + tid;
             const bool valid = j < fs;
-            const uint32_t e = valid ? S.front[cur][j] : 0u;
+            const uint32_t e = valid ? (rg ? gfr[(size_t)cur * gcap + j] : S.front[cur][j]) : 0u;
             const int c = (int)(e & kCellMask);
             const int fi = (e & kFlagIon) ? 1 : 0, fk = (e & kFlagImg) ? 1 : 0;
             const uint32_t open = (e >> kMaskSh) & 3u, dir = (e >> kDirSh) & 3u;
@@ -702,9 +731,17 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
             buf ^= 1;
             const int tf = (int)(tot & 0xffff), tn = (int)((tot >> 16) & 0xffff);
             const int ts = (int)((tot >> 32) & 0xffff), tg = (int)(tot >> 48);
-            if (next_n + 8 * ts > TS::FCAP || nflag + tg > 4) {  // uniform
+            if (nflag + tg > 4) {  // uniform
                 failed = true;
                 break;
+            }
+            if (next_n + 8 * ts > (wg ? gcap : lcap)) {  // uniform
+                if (wg || next_n + 8 * ts > gcap) {
+                    failed = frontier_full = true;
+                    break;
+                }
+                for (int k = tid; k < next_n; k += BLOCK) gfr[(size_t)(cur ^ 1) * gcap + k] = S.front[cur ^ 1][k];
+                wg = true;
             }
             const uint32_t flags = e & (kFlagIon | kFlagImg);
             if (kf) S.farl[far_n + (int)(before & 0xffff) + __popcll(bf & lt)] = (uint32_t)c | (farb << kMaskSh);
@@ -724,7 +761,8 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
                     const uint32_t fl = (d == dig_i ? kFlagIon : 0u) | (d == dig_k ? kFlagImg : 0u);
-                    S.front[cur ^ 1][o + d] = (uint32_t)(m.y + d) | masks | fl;
+                    if (wg) gfr[(size_t)(cur ^ 1) * gcap + o + d] = (uint32_t)(m.y + d) | masks | fl;
+                    else S.front[cur ^ 1][o + d] = (uint32_t)(m.y + d) | masks | fl;
                 }
             }
             far_n += tf; near_n += tn; nflag += tg; next_n += 8 * ts;
@@ -732,9 +770,10 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
         __syncthreads();  // the next level reads what this one wrote
         cur ^= 1;
         fs = next_n;
+        rg = wg;
     }
     if (failed) {
-        if (tid == 0) S.err = kErrStack;
+        if (tid == 0) S.err = frontier_full ? kErrFrontier : kErrStack;
         __syncthreads();
         return level;
     }
@@ -1086,7 +1125,12 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     double pot[2];
     const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook, MS.fs0, MS.level0, pot);
     (void)levels;
-    if (S.err) { out.stop = S.err == kErrStack ? -7 : -8; out.detail = S.err; __syncthreads(); return out; }
+    if (S.err) {
+        out.stop = (S.err == kErrStack || S.err == kErrFrontier) ? -7 : -8;
+        out.detail = S.err;
+        __syncthreads();
+        return out;
+    }
     if (th >= 0 && th < nps) {
         while (MS.plen[th] == 0 && my_level < kMaxLevels) step(th, my_level++);
         if (MS.plen[th] == 0) { MS.err = kErrPathDepth; MS.plen[th] = 1; MS.path[th][0] = 0; }
@@ -1279,16 +1323,19 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
     constexpr int NTG = kEnergyTargets;
     __shared__ Trav<NTG, kEnergyBlock> S;
     __shared__ Rep Rs;
+    __shared__ int cnt2[2];
     fill_mi(S);
     load_rep(Rs, reps + r);
     __syncthreads();
-    const int t0 = blockIdx.x * NTG;
-    const int nv = min(NTG, Rs.n - t0);
     const int tid = threadIdx.x;
     const bool imgs = Rs.images != 0;
-    if (tid < NTG) {
-        const int ion = t0 + tid;
+    const int ngroups = (Rs.n + NTG - 1) / NTG;
+    // one group of targets per workgroup, or several when the grid is bounded (HBM frontier regions)
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int t0 = grp * NTG;
+        const int nv = min(NTG, Rs.n - t0);
         if (tid < nv) {
+            const int ion = t0 + tid;
             const double4 si = Rs.src[ion];
             const double4 mo = imgs ? Rs.src[Rs.n + ion] : make_double4(0, 0, 0, 0);
             S.tx[tid] = si.x; S.ty[tid] = si.y; S.tz[tid] = si.z;
@@ -1298,24 +1345,24 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
             S.es_i[tid] = si; S.es_k[tid] = mo;
             S.front[0][tid] = pack(0, tid, kFlagIon | (imgs ? kFlagImg : 0u));
         }
-    }
-    if (tid == 0) { S.ovl_t = -1; S.ovl_ex = -1; S.n_ovl = 0; S.err = 0; S.overlap = 0; S.coincide = 0; }
-    __syncthreads();
-    __shared__ int cnt2[2];
-    traverse<NTG, kEnergyBlock>(Rs, S, nv, cnt2, [](int) {});
-    if (tid < nv) {
-        const int ion = t0 + tid;
-        const double4 si = Rs.src[ion];
-        const double ph = S.err ? __builtin_nan("") : S.res[tid];
-        if (S.err && tid == 0) reps[r].err_detail = S.err;
-        double e = 0.5 * si.w * ph;
-        if (Rs.geom == 1) {
-            const double r2 = si.x * si.x + si.y * si.y + si.z * si.z;
-            if (imgs) e += 0.5 * Rs.gamma * Rs.a * si.w * si.w / (r2 - Rs.a2);
-            if (Rs.Qc != 0.0) e += Rs.Qc * si.w / sqrt(r2);
+        if (tid == 0) { S.ovl_t = -1; S.ovl_ex = -1; S.n_ovl = 0; S.err = 0; S.overlap = 0; S.coincide = 0; }
+        __syncthreads();
+        traverse<NTG, kEnergyBlock>(Rs, S, nv, cnt2, [](int) {});
+        if (tid < nv) {
+            const int ion = t0 + tid;
+            const double4 si = Rs.src[ion];
+            const double ph = S.err ? __builtin_nan("") : S.res[tid];
+            if (S.err && tid == 0) reps[r].err_detail = S.err;
+            double e = 0.5 * si.w * ph;
+            if (Rs.geom == 1) {
+                const double r2 = si.x * si.x + si.y * si.y + si.z * si.z;
+                if (imgs) e += 0.5 * Rs.gamma * Rs.a * si.w * si.w / (r2 - Rs.a2);
+                if (Rs.Qc != 0.0) e += Rs.Qc * si.w / sqrt(r2);
+            }
+            if (phi) phi[ion] = ph;
+            eterm[ion] = e;
         }
-        if (phi) phi[ion] = ph;
-        eterm[ion] = e;
+        __syncthreads();  // the next group reuses the traversal state
     }
 }
 
@@ -1494,11 +1541,18 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
     __syncthreads();
     const Rep& R = Rs;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    const int g0 = blockIdx.x * kGT;
-    if (g0 >= nion) return;
     const bool imgs = R.images != 0;
     const double half_lB = 0.5 * R.l_B;
-    {
+    // frontier entries past the LDS capacity go to this workgroup's HBM region: cells, then masks
+    uint32_t* const gfr = spill_region(R);
+    const int gcap = gfr ? (int)((R.spill_words - 2) / 6 < 0x7FFFFFFF ? (R.spill_words - 2) / 6 : 0x7FFFFFFF) : 0;
+    uint32_t* const gfc = gfr;
+    uint64_t* const gfm = gfr ? (uint64_t*)(gfr + 2 * (size_t)gcap) : nullptr;
+    const int lcap = R.fcap < GS::FCAP ? R.fcap : GS::FCAP;
+    const int ngroups = (nion + kGT - 1) / kGT;
+    // one group of 16 ions per workgroup, or several when the grid is bounded (HBM frontier regions)
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int g0 = grp * kGT;
         if (tid == 0) { S.nt = min(kGT, nion - g0); S.err = 0; }
         __syncthreads();
         const int nt = S.nt;
@@ -1530,7 +1584,7 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
         // ---- breadth-first traversal with target masks
         int cur = 0, fs = 1, far_n = 0, near_n = 0, buf = 0;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        bool failed = false;
+        bool failed = false, frontier_full = false, rg = false, wg = false;
         for (int level = 0; fs > 0 && !failed; ++level) {
             int next_n = 0;
             for (int base = 0; base < fs; base += kGradBlock) {
@@ -1542,8 +1596,8 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
                 }
                 const int j = base + tid;
                 const bool valid = j < fs;
-                const uint32_t ec = valid ? S.fc[cur][j] : 0u;
-                const uint64_t em = valid ? S.fm[cur][j] : 0ull;
+                const uint32_t ec = valid ? (rg ? gfc[(size_t)cur * gcap + j] : S.fc[cur][j]) : 0u;
+                const uint64_t em = valid ? (rg ? gfm[(size_t)cur * gcap + j] : S.fm[cur][j]) : 0ull;
                 const int c = (int)(ec & kCellMask);
                 uint32_t farb = 0, nearb = 0, copen = 0, cdir = 0;
                 int4 m = make_int4(0, -1, 0, 0);
@@ -1601,7 +1655,18 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
                 }
                 buf ^= 1;
                 const int tf = (int)(tot & 0xffff), tn = (int)((tot >> 16) & 0xffff), ts = (int)((tot >> 32) & 0xffff);
-                if (next_n + 8 * ts > GS::FCAP) { failed = true; break; }  // uniform
+                if (next_n + 8 * ts > (wg ? gcap : lcap)) {  // uniform
+                    if (wg || next_n + 8 * ts > gcap) {
+                        failed = frontier_full = true;
+                        break;
+                    }
+                    // the next level moves to HBM: what this level wrote so far first
+                    for (int k = tid; k < next_n; k += kGradBlock) {
+                        gfc[(size_t)(cur ^ 1) * gcap + k] = S.fc[cur ^ 1][k];
+                        gfm[(size_t)(cur ^ 1) * gcap + k] = S.fm[cur ^ 1][k];
+                    }
+                    wg = true;
+                }
                 if (kf) {
                     const int o = far_n + (int)(before & 0xffff) + __popcll(bf & lt);
                     S.farc[o] = (uint32_t)c;
@@ -1638,9 +1703,15 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
                             const int t = __builtin_ctz(rest);
                             if ((int)((dion >> (4 * t)) & 15u) == d) io |= 1u << t;
                         }
-                        S.fc[cur ^ 1][o + d] = (uint32_t)(m.y + d);
-                        S.fm[cur ^ 1][o + d] = (uint64_t)copen | ((uint64_t)cdir << 16) | ((uint64_t)im << 32) |
-                                               ((uint64_t)io << 48);
+                        const uint64_t mk = (uint64_t)copen | ((uint64_t)cdir << 16) | ((uint64_t)im << 32) |
+                                            ((uint64_t)io << 48);
+                        if (wg) {
+                            gfc[(size_t)(cur ^ 1) * gcap + o + d] = (uint32_t)(m.y + d);
+                            gfm[(size_t)(cur ^ 1) * gcap + o + d] = mk;
+                        } else {
+                            S.fc[cur ^ 1][o + d] = (uint32_t)(m.y + d);
+                            S.fm[cur ^ 1][o + d] = mk;
+                        }
                     }
                 }
                 far_n += tf; near_n += tn; next_n += 8 * ts;
@@ -1648,8 +1719,9 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
             __syncthreads();
             cur ^= 1;
             fs = next_n;
+            rg = wg;
         }
-        if (failed && tid == 0) S.err = kErrStack;
+        if (failed && tid == 0) S.err = frontier_full ? kErrFrontier : kErrStack;
         __syncthreads();
         grad_rows(R, S, far_n, near_n, L, G, half_lB, acc);
         // the far cell holding a target's own image: take the image's pair terms back out
@@ -1817,11 +1889,13 @@ void run_mc(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide) {
 void run_move(hipStream_t s, Rep* reps, int r, MoveIO* io) {
     hipLaunchKernelGGL(k_move, dim3(1), dim3(kMcBlock), 0, s, reps, r, io);
 }
-void run_energy(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm) {
-    const int grid = (n + kEnergyTargets - 1) / kEnergyTargets;
+void run_energy(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm, int max_grid) {
+    int grid = (n + kEnergyTargets - 1) / kEnergyTargets;
+    if (max_grid > 0 && grid > max_grid) grid = max_grid;
     hipLaunchKernelGGL(k_energy, dim3(grid), dim3(kEnergyBlock), 0, s, reps, r, phi, eterm);
 }
-void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq, double* eterm) {
+void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq, double* eterm,
+              int max_grid) {
     const size_t nl = (size_t)w.ncell * MSTR, ng = 4 * (size_t)w.nsrc;
     hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(4096, (nl + 255) / 256)), dim3(256), 0, s, w.L, nl);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(4096, (ng + 255) / 256)), dim3(256), 0, s,
@@ -1831,7 +1905,9 @@ void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, 
     hipLaunchKernelGGL(k_gscan, dim3(1), dim3(1024), 0, s, w.rank, w.nsrc);
     hipLaunchKernelGGL(k_gfill, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
                        (const int*)w.rank, w.islot);
-    hipLaunchKernelGGL(k_grad, dim3((w.n + kGT - 1) / kGT), dim3(kGradBlock), 0, s, reps, r, (const int*)w.islot, w.n,
+    int ggrid = (w.n + kGT - 1) / kGT;
+    if (max_grid > 0 && ggrid > max_grid) ggrid = max_grid;
+    hipLaunchKernelGGL(k_grad, dim3(ggrid), dim3(kGradBlock), 0, s, reps, r, (const int*)w.islot, w.n,
                        w.L, w.G, w.Gt, eterm);
     hipLaunchKernelGGL(k_adj_down, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
                        (const double*)w.L, w.G);

@@ -61,9 +61,11 @@ struct EvalOps {
     // wide = 1: 512-thread workgroups (one chain); 0: 256-thread workgroups, two per CU (replicas)
     void (*mc)(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide);
     void (*move)(hipStream_t s, Rep* reps, int r, MoveIO* io_dev);
-    void (*energy)(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm);
+    // max_grid > 0 bounds the number of workgroups (each then takes several target groups), so that
+    // every workgroup has an HBM frontier region
+    void (*energy)(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm, int max_grid);
     void (*grad)(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq,
-                 double* eterm);
+                 double* eterm, int max_grid);
 };
 const EvalOps* eval_ops(int p);
 

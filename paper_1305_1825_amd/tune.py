@@ -1,13 +1,17 @@
-"""Opening angle and expansion order at a fixed accuracy, picked by measurement.
+"""Opening angle, expansion order and minimum expansion number at a fixed
+accuracy, picked by measurement.
 
-For one system, every (theta, p) candidate is scored by the error E of eq. 4.1
-against the direct sum (the library at theta = 0) and, if E meets the target,
-by the Metropolis rate of a short chain on the GPU; the fastest candidate that
-meets the target wins.  The paper leaves theta, p and N_0 to the user (Sec. 4
-discusses their trade-off); this makes the choice for a given system and
-error.
+The paper leaves theta, p and N_0 to the user: Sec. 3.2 defines N_0 as the
+smallest cell population worth an expansion (smaller cells are summed
+directly), and Sec. 4 tunes it per p by timing.  Here every candidate is
+scored on one system by two errors against the direct sum (the library at
+theta = 0): the measure E of eq. 4.1 over the per-ion energies, and the
+relative error of the total energy.  For each theta the smallest p meeting
+the target on both is kept; for it, N_0 is swept and each setting that still
+meets the target is timed on a Metropolis chain on the GPU.  The fastest
+candidate wins.
 
-    python -m paper_1305_1825_amd.tune [--target 1e-4] [--moves 5000]
+    python -m paper_1305_1825_amd.tune [--workload colloid|replica] [--target 1e-4] [--moves 10000]
 """
 from __future__ import annotations
 
@@ -21,32 +25,29 @@ from . import bhmc
 from . import workloads as W
 
 
-def direct_phi(P, x, y, z, q):
-    t = bhmc.Tree(dict(P, theta=0.0), x, y, z, q)
-    _, _, dq = t.energy_grad()
+def direct_energies(P, x, y, z, q):
+    """Per-ion potentials and the total energy of the direct sum (theta = 0)."""
+    t = bhmc.Tree(dict(P, theta=0.0, n0=0), x, y, z, q)
+    E, phi = t.energy(with_phi=True)
     t.close()
-    dq = dq.cpu().numpy()
-    l = P["l_B"]
-    extra = np.zeros_like(q)
-    if P.get("geom", 0) == 1:
-        r2 = x * x + y * y + z * z
-        if P.get("images", 0):
-            gam = (P["eps_out"] - P["eps_in"]) / (P["eps_out"] + P["eps_in"])
-            extra += l * gam * P["a"] * q / (r2 - P["a"] ** 2)
-        extra += l * P.get("Q_center", 0.0) / np.sqrt(r2)
-    return (dq - extra) / l
+    return phi.cpu().numpy(), E
 
 
-def error_41(P, x, y, z, q, phi_d):
+def errors(P, x, y, z, q, phi_d, E_d):
+    """(E of eq. 4.1, |E_tree - E_dir| / |E_dir|) of the treecode with parameters P."""
     t = bhmc.Tree(P, x, y, z, q)
-    _, phi = t.energy(with_phi=True)
+    E, phi = t.energy(with_phi=True)
     t.close()
     V, Vt = q * phi_d, q * phi.cpu().numpy()
-    return float(np.sqrt(np.sum((V - Vt) ** 2) / np.sum(V ** 2)))
+    return float(np.sqrt(np.sum((V - Vt) ** 2) / np.sum(V ** 2))), abs(E - E_d) / abs(E_d)
 
 
 def chain_rate(P, x, y, z, q, moves, step, seed=0):
+    """Trial moves per second of one chain on the device (kernel time only)."""
     import torch
+    t = bhmc.Tree(P, x, y, z, q)
+    t.mc_run(seed=seed + 1, n_moves=min(500, moves), step=step)  # warm the kernel
+    t.close()
     t = bhmc.Tree(P, x, y, z, q)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -57,21 +58,30 @@ def chain_rate(P, x, y, z, q, moves, step, seed=0):
     return moves / dt
 
 
-def tune(P, x, y, z, q, target=1e-4, thetas=(0.3, 0.4, 0.5, 0.6, 0.7), ps=range(2, 11), moves=5000,
-         step=1.0):
-    phi_d = direct_phi(P, x, y, z, q)
+def tune(P, x, y, z, q, target=1e-4, thetas=(0.3, 0.4, 0.5, 0.6), ps=range(2, 11),
+         n0s=(0, 4, 8, 16, 32, 64), moves=10000, step=1.0, log=print):
+    phi_d, E_d = direct_energies(P, x, y, z, q)
     rows = []
     for theta in thetas:
         for p in ps:
-            Pc = dict(P, theta=theta, p=p)
-            E = error_41(Pc, x, y, z, q, phi_d)
-            row = {"theta": theta, "p": p, "E": E}
-            if E <= target:
-                row["moves_per_s"] = chain_rate(Pc, x, y, z, q, moves, step)
-            rows.append(row)
-            print(json.dumps(row), flush=True)
-            if E <= target:
-                break  # a larger p at this theta is only slower
+            Pc = dict(P, theta=theta, p=p, n0=0)
+            e41, erel = errors(Pc, x, y, z, q, phi_d, E_d)
+            if max(e41, erel) > target:
+                row = {"theta": theta, "p": p, "n0": 0, "E_4_1": e41, "E_rel": erel}
+                rows.append(row)
+                log(json.dumps(row))
+                continue
+            # the smallest p meeting the target at this theta: sweep N_0
+            for n0 in n0s:
+                Pn = dict(Pc, n0=n0)
+                if n0:
+                    e41, erel = errors(Pn, x, y, z, q, phi_d, E_d)
+                row = {"theta": theta, "p": p, "n0": n0, "E_4_1": e41, "E_rel": erel}
+                if max(e41, erel) <= target:
+                    row["moves_per_s"] = chain_rate(Pn, x, y, z, q, moves, step)
+                rows.append(row)
+                log(json.dumps(row))
+            break
     ok = [r for r in rows if "moves_per_s" in r]
     best = max(ok, key=lambda r: r["moves_per_s"]) if ok else None
     return best, rows
@@ -79,12 +89,20 @@ def tune(P, x, y, z, q, target=1e-4, thetas=(0.3, 0.4, 0.5, 0.6, 0.7), ps=range(
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="colloid", choices=("colloid", "replica"))
     ap.add_argument("--target", type=float, default=1e-4)
-    ap.add_argument("--moves", type=int, default=5000)
+    ap.add_argument("--moves", type=int, default=10000)
     args = ap.parse_args()
-    c = W.config_colloid_10k()
-    best, _ = tune(c["params"], c["x"], c["y"], c["z"], c["q"], target=args.target, moves=args.moves,
-                   step=c["step"])
+    if args.workload == "colloid":
+        c = W.config_colloid_10k()
+        P, x, y, z, q, step = c["params"], c["x"], c["y"], c["z"], c["q"], c["step"]
+    else:  # a median-sized replica of the 256-replica workload
+        sizes = [int(v) for v in W.replica_sizes(256, seed=0)]
+        r = int(np.argsort(sizes)[len(sizes) // 2])
+        P, x, y, z, q = W.batched_replica(r, sizes[r], seed=0)
+        step = 1.0
+    best, _ = tune(P, x, y, z, q, target=args.target, moves=args.moves, step=step,
+                   log=lambda s: print(s, flush=True))
     print(json.dumps({"best": best}), flush=True)
 
 
