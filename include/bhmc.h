@@ -152,6 +152,19 @@ bhmc_status bhmc_info_get(bhmc_tree* tree, int32_t replica, bhmc_info* info);
  * phi_dev (nullable): dev, n values, receives phi_i. */
 bhmc_status bhmc_energy(bhmc_tree* tree, int32_t replica, double* E_host, double* phi_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the energy of
+ * bhmc_energy without any allocation or host synchronisation.  The per-ion
+ * energy terms are kept in a fixed device array of the library (4 MiB per
+ * device, held until the process ends), so replicas of at most 524,288 ions
+ * are accepted (EINVAL beyond).  E_dev: dev, 1 value, receives E; phi_dev
+ * (nullable): dev, n values.  Work is enqueued on the handle's stream and the
+ * call returns at once; a traversal that failed leaves NaN in *E_dev (host
+ * errors are returned as usual).  Every handle on a device shares the one
+ * array, which keeps the last call's contents: calls that overlap on one
+ * device (concurrent streams or threads) race. */
+bhmc_status bhmc_energy_noalloc(bhmc_tree* tree, int32_t replica, double* E_dev, double* phi_dev);
+
 /* Energy change of moving ion i of replica 0 to r_new (host, 3 values), on
  * the committed tree (Sec. 1: the particle's energy evaluated twice):
  *   dE = l_B q_i [phi(r_new) - phi(r_i)] + exact self-image change

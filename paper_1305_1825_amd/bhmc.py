@@ -66,6 +66,7 @@ SIGNATURES = {
     "bhmc_replicas": [_v],
     "bhmc_info_get": [_v, C.c_int32, C.POINTER(Info)],
     "bhmc_energy": [_v, C.c_int32, _d, _v],
+    "bhmc_energy_noalloc": [_v, C.c_int32, _v, _v],
     "bhmc_delta_energy": [_v, C.c_int64, _d, _d, _i32],
     "bhmc_commit_move": [_v, C.c_int64, _d],
     "bhmc_mc_run": [_v, C.c_int32, C.c_uint64, C.c_uint64, C.c_int64, C.c_double, _v, C.POINTER(Stats)],
@@ -197,6 +198,12 @@ class Tree:
         phi = torch.empty(self.n_per[replica], dtype=torch.float64, device=self.device) if with_phi else None
         _check(lib().bhmc_energy(self.h, replica, C.byref(E), phi.data_ptr() if with_phi else None), "energy")
         return (E.value, phi) if with_phi else E.value
+
+    def energy_noalloc(self, E_out, phi_out=None, replica=0):
+        """Energy into the device tensor E_out (one float64) without allocation or
+        synchronisation; phi_out (optional, n float64 on the device) gets phi_i."""
+        _check(lib().bhmc_energy_noalloc(self.h, replica, E_out.data_ptr(),
+                                         phi_out.data_ptr() if phi_out is not None else None), "energy_noalloc")
 
     def delta_energy(self, i, r_new):
         rn = (C.c_double * 3)(*[float(v) for v in r_new])

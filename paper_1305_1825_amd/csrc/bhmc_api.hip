@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -93,6 +94,33 @@ void launch_sum(hipStream_t s, const double* v, int n, double scale, double* out
 
 using bhmc::Rep;
 
+// ------------------------------------------------------------ fixed scratch memory
+// Per-ion energy terms of bhmc_energy_noalloc live in this file-scope device
+// array instead of library allocations.  In host code the name stands for a
+// host-side shadow, not a device address: kernels and copies only ever get the
+// address hipGetSymbolAddress returns, resolved once per device when the first
+// handle is created on it (each device holds its own copy of the array).
+constexpr int kScratchDoubles = 1 << 19;  // 4 MiB: energy terms of up to 524,288 ions
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the scratch array on the current device (null on failure).
+static double* scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_dev[dev] = (double*)ptr;
+    }
+    return g_scratch_dev[dev];
+}
+
 // ------------------------------------------------------------ handle
 struct bhmc_tree {
     int R = 0, p = 0, nterms = 0, mstride = 0;
@@ -114,6 +142,7 @@ struct bhmc_tree {
     double* eterm = nullptr; int eterm_n = 0;
     char* gwork = nullptr; size_t gwork_bytes = 0;  // gradient workspace
     double* scalar = nullptr;
+    double* scratch = nullptr;       // device address of the fixed scratch array on the handle's device
     // HBM frontier regions, allocated the first time a traversal level outgrows its LDS capacity
     uint32_t* spill = nullptr;
     int spill_regions = 0;
@@ -460,6 +489,8 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     int dev = 0, ncu = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    t->scratch = scratch_address(dev);
+    if (!t->scratch) return bail(fail(BHMC_EHIP, "cannot resolve the scratch array on device %d", dev));
     // one replica: one wide workgroup; replicas: two 256-thread workgroups per CU.  A handle
     // always runs the same kernel, so a replica's chain does not depend on how it is advanced.
     t->mc_wide = R == 1 ? 1 : 0;
@@ -577,6 +608,24 @@ extern "C" bhmc_status bhmc_energy(bhmc_tree* t, int32_t replica, double* E_host
         bool again = false;
         if ((st = finish_energy(t, replica, n, E_host, "energy", &again)) || !again) return st;
     }
+}
+
+// The energy of bhmc_energy with its per-ion terms in the fixed scratch array and
+// the total written to device memory: nothing is allocated and nothing waits
+// for the device, so the call can be captured in a graph.
+extern "C" bhmc_status bhmc_energy_noalloc(bhmc_tree* t, int32_t replica, double* E_dev, double* phi_dev) {
+    bhmc_status st = check_rep(t, replica);
+    if (st) return st;
+    if (!E_dev) return fail(BHMC_EINVAL, "null energy output");
+    const int n = t->host[replica].n;
+    if (n > kScratchDoubles)
+        return fail(BHMC_EINVAL, "replica %d has %d ions; the allocation-free energy takes at most %d", replica, n,
+                    kScratchDoubles);
+    if (!t->scratch) return fail(BHMC_EHIP, "scratch array not resolved");
+    t->ops->energy(t->stream, t->reps, replica, n, phi_dev, t->scratch, energy_grid_bound(t));
+    bhmc::launch_sum(t->stream, t->scratch, n, t->host[replica].l_B, E_dev);
+    HIP_TRY(hipGetLastError());
+    return BHMC_OK;
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
