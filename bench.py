@@ -140,7 +140,7 @@ def copy_probe(mib=2048, reps=10):
     return dict(gbs=gbs, bytes_per_copy=2 * (mib << 20), ms_per_copy=ms)
 
 
-def run_plain(c, steps, warmup, tune=True):
+def run_plain(c, steps, warmup, tune=True, moves_per_round=0):
     import torch
     from paper_1305_1825_amd import bhmc
     P = c["params"]
@@ -155,9 +155,10 @@ def run_plain(c, steps, warmup, tune=True):
     def one_step(timed):
         nonlocal last, final
         t = bhmc.Tree(P, x, y, z, q)
-        if tune and not shape:  # the first step picks the launch shape, later steps reuse it
+        shape["moves_per_round"] = t.set_moves_per_round(moves_per_round)
+        if tune and "choice" not in shape:  # the first step picks the launch shape, later steps reuse it
             shape.update(t.autotune(seed=c["seed"], step=c["step"], trial_moves=1000))
-        elif shape:
+        elif "choice" in shape:
             t.set_shape(shape["choice"])
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -182,12 +183,13 @@ def run_plain(c, steps, warmup, tune=True):
     return dict(wall=wall, mc_ms=mc_ms, stats=last, final=final, autotune=shape)
 
 
-def chain_kernel_rate(P, x, y, z, q, moves, seed=0, step=1.0, replica=0):
-    """One chain alone through the plain single-chain kernel (512 threads on one CU),
-    trial moves per second of kernel time."""
+def chain_kernel_rate(P, x, y, z, q, moves, seed=0, step=1.0, replica=0, moves_per_round=1):
+    """One chain alone (512 threads on one CU), trial moves per second of kernel time;
+    moves_per_round = 1 is the plain single-chain kernel (one move at a time)."""
     import torch
     from paper_1305_1825_amd import bhmc
     t = bhmc.Tree(P, x, y, z, q)
+    t.set_moves_per_round(moves_per_round)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
@@ -247,9 +249,11 @@ def run_batched(R, sweeps, params, seed=0):
     rm = order[R // 2]
     P, x, y, z, q = reps[rm]
     plain = chain_kernel_rate(Ps[rm], x, y, z, q, moves=sizes[rm], seed=seed, replica=0)
+    rounds = chain_kernel_rate(Ps[rm], x, y, z, q, moves=sizes[rm], seed=seed, replica=0, moves_per_round=0)
     return dict(moves=moves, wall=wall, moves_per_s=moves / wall, replicas=R, sweeps=sweeps, rebuilds=rebuilds,
                 n_min=min(sizes), n_max=max(sizes), n_total=sum(sizes), autotune=tune, params=params,
                 accuracy=acc, plain_median_replica=dict(replica=rm, n=sizes[rm], **plain),
+                rounds_median_replica=dict(replica=rm, n=sizes[rm], **rounds),
                 ratio_vs_plain=(moves / wall) / plain["moves_per_s"])
 
 
@@ -321,13 +325,14 @@ def run_large(sweeps, grad_each=True):
     wall = sum(sweep_s)
     c0 = reps[0]
     plain = chain_kernel_rate(c0["params"], c0["x"], c0["y"], c0["z"], c0["q"], moves=20000)
+    rounds = chain_kernel_rate(c0["params"], c0["x"], c0["y"], c0["z"], c0["q"], moves=20000, moves_per_round=0)
     acc = accuracy(c0["params"], c0["x"], c0["y"], c0["z"], c0["q"])
     return dict(workload="64 replicas x N=199999 (2:1, a=20, Q=-200, shell 20.5<r<200) + images, "
                          "theta=0.5, p=8, leaf 32", replicas=R, sweeps=sweeps, moves=moves,
                 wall=wall, moves_per_s=moves / wall, build_s=build_s, autotune=tune,
                 gradient_s_per_sweep=(float(np.mean(grad_s)) if grad_s else None),
                 gradient_ms_per_replica=(1000.0 * float(np.mean(grad_s)) / R if grad_s else None),
-                plain_one_replica=plain, ratio_vs_plain=(moves / wall) / plain["moves_per_s"],
+                plain_one_replica=plain, rounds_one_replica=rounds, ratio_vs_plain=(moves / wall) / plain["moves_per_s"],
                 accuracy_replica0={k: acc[k] for k in ("E_4_1", "E_rel", "meets_1e-4")})
 
 
@@ -459,11 +464,16 @@ def main():
                      "achievable": achievable, "frac_achievable": achieved / achievable,
                      "per_cu": {"peak": CU_L2_GBS, "frac": achieved / CU_L2_GBS,
                                 "note": "one workgroup on one CU: bytes through that CU over its L2 path"},
-                     "kernel": "k_mc<512> (p=%d)" % g["p"], "algorithmic_bytes_per_move": ab["per_move"],
+                     "kernel": "k_mcb<512> (p=%d, rounds of %d trial moves)" % (g["p"], res["autotune"].get("moves_per_round", 1)),
+                     "algorithmic_bytes_per_move": ab["per_move"],
                      "per_move_counts": {k: ab[k] for k in ("visited", "far", "near", "eval_fraction")}},
         "copy_probe": probe,
         "csrc": csrc_hash(),
     }
+    log("the headline chain one move at a time (plain single-chain kernel)")
+    plain_c = chain_kernel_rate(c["params"], c["x"], c["y"], c["z"], c["q"], moves=c["moves"], seed=c["seed"])
+    out["plain_single_move_chain"] = plain_c
+    out["rounds_vs_single_move"] = (c["moves"] / (mc_ms / 1000.0)) / plain_c["moves_per_s"]
     log("accuracy of the headline against the direct sum")
     acc = {"start": accuracy(c["params"], c["x"], c["y"], c["z"], c["q"])}
     fx, fy, fz, fq = res["final"]

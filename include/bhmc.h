@@ -249,6 +249,32 @@ bhmc_status bhmc_set_launch_shape(bhmc_tree* tree, int32_t shape);
 bhmc_status bhmc_energy_grad(bhmc_tree* tree, int32_t replica, double* dEdr_dev, double* dEdq_dev,
                              double* E_host);
 
+/* Trial moves evaluated together by bhmc_mc_run and bhmc_batch_sweep (and the
+ * autotuner).  moves = 1: one move at a time (evaluate, decide, commit).
+ * moves = 0 (the default) or > 1: rounds of up to that many consecutive moves
+ * of distinct ions (at most 8 for p <= 6, 4 for p <= 8, 2 above), evaluated in
+ * one traversal of the tree as it stands at the start of the round and then
+ * decided and committed in order, each energy change corrected exactly for the
+ * moves accepted before it in the round (Sec. 3.2 with N_0 = 0: the
+ * traversal's decisions depend only on geometry and occupancy, so an accepted
+ * move changes a later move's potentials only through its own contributions).
+ * The chain -- accept stream, positions, statistics -- is the same as with one
+ * move at a time, up to the rounding of the energy sums.  Replicas with N_0 > 0
+ * always run one move at a time.  effective (nullable, host) receives the
+ * moves per round the handle will use. */
+bhmc_status bhmc_set_moves_per_round(bhmc_tree* tree, int32_t moves, int32_t* effective);
+
+/* Phase timers of the batched Metropolis kernel, present only in a library
+ * built with phase timers (python -m paper_1305_1825_amd.build --phase-timers):
+ * ticks of the device's constant clock summed over every round run on this
+ * handle's expansion order -- set-up, traversal levels, corrected moments and
+ * scan, far cells, near leaves, hard cores below far cells, path descents,
+ * corrections, decisions, leaf index arrays, moments -- then the number of
+ * rounds and of moves.  ticks: host, n values; count (nullable, host) receives
+ * the number of counters (0 for a library built without timers, which then
+ * writes nothing).  reset = 1 clears them after reading. */
+bhmc_status bhmc_phase_ticks(bhmc_tree* tree, uint64_t* ticks, int32_t n, int32_t reset, int32_t* count);
+
 /* Frontier capacity of the breadth-first MAC traversals (Sec. 3.2).  A level
  * keeps up to lds_entries frontier entries on chip (64..4096; 4096 after
  * build).  With allow_spill = 1 (the default) a level that outgrows them

@@ -79,6 +79,7 @@ def _declare(L):
         "orc_tree_free": (None, [_T]),
         "orc_tree_phi": (C.c_double, [_T, _d, C.POINTER(C.c_int), C.c_int]),
         "orc_tree_phi_counts": (C.c_double, [_T, _d, C.POINTER(C.c_int), C.c_int, _i64]),
+        "orc_tree_far_magnitude": (C.c_double, [_T, _d, C.POINTER(C.c_int), C.c_int]),
         "orc_tree_delta": (C.c_double, [_T, C.c_int64, _d, C.POINTER(C.c_int), _i64]),
         "orc_tree_commit": (C.c_int, [_T, C.c_int64, _d]),
         "orc_tree_energy": (C.c_double, [_T, _d]),
@@ -314,6 +315,12 @@ class Tree:
         c = np.zeros(3, dtype=np.int64)
         v = lib().orc_tree_phi_counts(self.h, _ptr(r, _d), ex, len(exclude), _ptr(c, _i64))
         return v, c
+
+    def far_magnitude(self, xt, exclude=()):
+        """sum over the expanded cells of sum_n |T_n M'_n| at one target."""
+        r = _f64(xt)
+        ex = (C.c_int * max(len(exclude), 1))(*[int(e) for e in exclude])
+        return lib().orc_tree_far_magnitude(self.h, _ptr(r, _d), ex, len(exclude))
 
     def certificate(self, xt, exclude=()):
         r = _f64(xt)

@@ -600,6 +600,7 @@ typedef struct {
     int coincide;            /* a near source at distance exactly 0            */
     double *T, *mono, *Mp;
     ocount cnt;
+    double farabs;           /* sum over far cells of sum_n |T_n M'_n|            */
 } vstate;
 
 static void direct_cell(const otree *t, int c, const double *xt, vstate *v) {
@@ -636,7 +637,10 @@ static double far_value(const otree *t, int c, const double *xt, vstate *v) {
     }
     taylor(t->P.p, t->mi, A->cx - xt[0], A->cy - xt[1], A->cz - xt[2], v->T);
     double val = 0.0;
-    for (int k = 0; k < t->nterms; ++k) val += v->T[k] * v->Mp[k];
+    for (int k = 0; k < t->nterms; ++k) {
+        val += v->T[k] * v->Mp[k];
+        v->farabs += fabs(v->T[k] * v->Mp[k]);
+    }
     return val;
 }
 
@@ -664,8 +668,15 @@ static void visit(const otree *t, int c, const double *xt, vstate *v) {
     }
 }
 
-/* potential at xt from all sources except ex[0..nex) */
+/* potential at xt from all sources except ex[0..nex); farabs (nullable) receives
+ * the sum over far cells of sum_n |T_n M'_n| */
+static double tree_phi_abs(otree *t, const double *xt, const int *ex, int nex, int *coincide,
+                           double *farabs);
 static double tree_phi(otree *t, const double *xt, const int *ex, int nex, int *coincide) {
+    return tree_phi_abs(t, xt, ex, nex, coincide, NULL);
+}
+static double tree_phi_abs(otree *t, const double *xt, const int *ex, int nex, int *coincide,
+                           double *farabs) {
     vstate v;
     memset(&v, 0, sizeof(v));
     v.ex = ex; v.nex = nex;
@@ -676,7 +687,17 @@ static double tree_phi(otree *t, const double *xt, const int *ex, int nex, int *
     free(v.T); free(v.mono); free(v.Mp);
     t->cnt.visited += v.cnt.visited; t->cnt.far += v.cnt.far; t->cnt.near_src += v.cnt.near_src;
     if (coincide) *coincide = v.coincide;
+    if (farabs) *farabs = v.farabs;
     return nval(&v.acc);
+}
+
+/* Magnitude of the far field at xt: sum over the cells the traversal expands of
+ * sum_n |T_n(r_A - x) M'^n_A| (eq. 3.3 term by term), the scale of the rounding of
+ * a far-field evaluation in a lower precision. */
+double orc_tree_far_magnitude(otree *t, const double *xt, const int *ex, int nex) {
+    double fa = 0.0;
+    tree_phi_abs(t, xt, ex, nex, NULL, &fa);
+    return fa;
 }
 
 double orc_tree_phi(otree *t, const double *xt, const int *ex, int nex) {

@@ -75,6 +75,8 @@ SIGNATURES = {
     "bhmc_set_launch_shape": [_v, C.c_int32],
     "bhmc_energy_grad": [_v, C.c_int32, _v, _v, _d],
     "bhmc_set_frontier_capacity": [_v, C.c_int32, C.c_int32],
+    "bhmc_set_moves_per_round": [_v, C.c_int32, C.POINTER(C.c_int32)],
+    "bhmc_phase_ticks": [_v, C.POINTER(C.c_uint64), C.c_int32, C.c_int32, C.POINTER(C.c_int32)],
     "bhmc_get_state": [_v, C.c_int32, _v, _v, _v, _v],
     "bhmc_rebuild": [_v, C.c_int32],
     "bhmc_refresh_moments": [_v, C.c_int32],
@@ -254,6 +256,23 @@ class Tree:
         E = C.c_double()
         _check(lib().bhmc_energy_grad(self.h, replica, g.data_ptr(), gq.data_ptr(), C.byref(E)), "energy_grad")
         return E.value, g, gq
+
+    def set_moves_per_round(self, moves=0):
+        """1: one trial move at a time; 0 or more: rounds of that many (0 = the most the
+        order allows).  Returns the moves per round the handle will use."""
+        eff = C.c_int32()
+        _check(lib().bhmc_set_moves_per_round(self.h, int(moves), C.byref(eff)), "set_moves_per_round")
+        return int(eff.value)
+
+    PHASES = ("setup", "levels", "flagged_scan", "far", "near", "overlap", "paths", "corrections", "decisions",
+              "slots", "moments", "rounds", "moves")
+
+    def phase_ticks(self, reset=True):
+        """Phase timers of the batched kernel (a library built with phase timers), else {}."""
+        arr = (C.c_uint64 * 32)()
+        cnt = C.c_int32()
+        _check(lib().bhmc_phase_ticks(self.h, arr, 32, 1 if reset else 0, C.byref(cnt)), "phase_ticks")
+        return {self.PHASES[k]: int(arr[k]) for k in range(min(cnt.value, len(self.PHASES)))}
 
     def set_frontier_capacity(self, lds_entries=4096, allow_spill=True):
         _check(lib().bhmc_set_frontier_capacity(self.h, int(lds_entries), 1 if allow_spill else 0),

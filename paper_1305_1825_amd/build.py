@@ -46,32 +46,41 @@ def _compile(src: str, obj: str, defines=()) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Compile every translation unit and link libbhmc.so; always recompiles."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, phase_timers: bool = False) -> str:
+    """Compile every translation unit and link libbhmc.so (or, with phase_timers, the
+    instrumented libbhmc_phase.so beside it); always recompiles."""
+    build_dir = BUILD + ("_phase" if phase_timers else "")
+    lib_path = os.path.join(HERE, "libbhmc_phase.so") if phase_timers else LIB
+    extra = ("BHMC_PHASE_TIMERS",) if phase_timers else ()
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
     units = [
-        (os.path.join(CSRC, "bhmc_build.hip"), os.path.join(BUILD, "bhmc_build.o"), ()),
-        (os.path.join(CSRC, "bhmc_api.hip"), os.path.join(BUILD, "bhmc_api.o"), ()),
+        (os.path.join(CSRC, "bhmc_build.hip"), os.path.join(build_dir, "bhmc_build.o"), extra),
+        (os.path.join(CSRC, "bhmc_api.hip"), os.path.join(build_dir, "bhmc_api.o"), extra),
     ]
     for p in range(P_MAX + 1):
-        units.append((os.path.join(CSRC, "bhmc_eval.hip"), os.path.join(BUILD, "bhmc_eval_p%d.o" % p),
-                      ("BHMC_P=%d" % p,)))
+        units.append((os.path.join(CSRC, "bhmc_eval.hip"), os.path.join(build_dir, "bhmc_eval_p%d.o" % p),
+                      ("BHMC_P=%d" % p,) + extra))
+
+    def order_of(u):
+        ps = [d for d in u[2] if d.startswith("BHMC_P=")]
+        return -int(ps[0].split("=")[1]) if ps else 0
+
     # the largest orders take longest: start them first
-    units.sort(key=lambda u: -int(u[2][0].split("=")[1]) if u[2] else 0)
+    units.sort(key=order_of)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda u: _compile(*u), units))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib_path + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (res.stdout, res.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib_path)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, phase_timers="--phase-timers" in sys.argv[1:])
     sys.exit(0)

@@ -150,6 +150,8 @@ struct bhmc_tree {
     int fcap = 4096;                 // frontier entries a level keeps in LDS
     int allow_spill = 1;
     bool energy_bounded = false;     // energy / gradient launches keep their grid within the regions
+    int moves_per_round = 0;         // 0: as many as the order allows; 1: the move-by-move kernel
+    bool all_n0_zero = true;         // the batched kernel needs N_0 = 0 on every replica
     int mc_grid = 1;
     int mc_wide = 1;                 // one replica: the 512-thread Metropolis kernel
     hipGraph_t graph = nullptr;
@@ -459,6 +461,8 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     t->arena1.assign(R, nullptr);
     t->arena2.assign(R, nullptr);
     t->ops = bhmc::eval_ops(t->p);
+    for (int r = 0; r < R; ++r)
+        if (params[r].n0 != 0) t->all_n0_zero = false;
     std::vector<long long> off(R);
     long long acc = 0;
     for (int r = 0; r < R; ++r) { fill_rep(t->host[r], params[r], n_per[r]); off[r] = acc; acc += n_per[r]; }
@@ -722,6 +726,23 @@ extern "C" bhmc_status bhmc_commit_move(bhmc_tree* tree, int64_t i, const double
     return BHMC_OK;
 }
 
+// Moves per round the handle's Metropolis launches take (1 = the move-by-move kernel).
+static int rounds_of(const bhmc_tree* t) {
+    if (t->moves_per_round == 1 || !t->all_n0_zero) return 1;
+    const int cap = t->ops->moves_per_round;
+    return t->moves_per_round > 1 && t->moves_per_round < cap ? t->moves_per_round : cap;
+}
+
+static void launch_mc(bhmc_tree* t, hipStream_t s, bhmc::McArgs a, int grid, int wide) {
+    const int bm = rounds_of(t);
+    if (bm <= 1) {
+        t->ops->mc(s, t->reps, a, grid, wide);
+    } else {
+        a.bm = bm;
+        t->ops->mcb(s, t->reps, a, grid, wide);
+    }
+}
+
 static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArgs& base, long long* rebuilds) {
     long long last_stop = -1;
     for (;;) {
@@ -731,7 +752,7 @@ static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArg
         bhmc_status st0 = h2d(t, t->list_one, &r, sizeof(int));
         if (st0) return st0;
         bhmc::launch_reset_queue(t->stream, t->queue);
-        t->ops->mc(t->stream, t->reps, a, 1, t->mc_wide);
+        launch_mc(t, t->stream, a, 1, t->mc_wide);
         HIP_TRY(hipGetLastError());
         bhmc_status st = download(t);
         if (st) return st;
@@ -841,7 +862,7 @@ static bhmc_status finish_sweep(bhmc_tree* t, const bhmc::McArgs& base, std::vec
         a.list = t->list_rest;
         a.nlist = (int)rest.size();
         bhmc::launch_reset_queue(t->stream, t->queue);
-        t->ops->mc(t->stream, t->reps, a, std::min((int)rest.size(), t->mc_grid), t->mc_wide);
+        launch_mc(t, t->stream, a, std::min((int)rest.size(), t->mc_grid), t->mc_wide);
         HIP_TRY(hipGetLastError());
     }
 }
@@ -877,7 +898,7 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
             if (t->graph) { hipGraphDestroy(t->graph); t->graph = nullptr; }
             HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
             bhmc::launch_sweep_prep(gs, t->reps, t->R, t->queue, t->sweep_add);
-            t->ops->mc(gs, t->reps, a, t->mc_grid, t->mc_wide);
+            launch_mc(t, gs, a, t->mc_grid, t->mc_wide);
             HIP_TRY(hipStreamEndCapture(gs, &t->graph));
             HIP_TRY(hipGraphInstantiate(&t->gexec, t->graph, nullptr, nullptr, 0));
             t->graph_ok = true; t->graph_seed = seed; t->graph_step = step;
@@ -889,7 +910,7 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
             if (gs != t->stream) HIP_TRY(hipStreamSynchronize(gs));
         } else {
             bhmc::launch_sweep_prep(t->stream, t->reps, t->R, t->queue, t->sweep_add);
-            t->ops->mc(t->stream, t->reps, a, t->mc_grid, t->mc_wide);
+            launch_mc(t, t->stream, a, t->mc_grid, t->mc_wide);
         }
         HIP_TRY(hipGetLastError());
         if ((st = finish_sweep(t, a, rebuilds, last_stop))) return st;
@@ -960,7 +981,7 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
         bhmc::launch_reset_queue(t->stream, t->queue);
         const int grid = std::max(1, std::min(t->R, sh.per_cu * ncu));
         if (hipEventRecord(e0, t->stream) != hipSuccess) { st = fail(BHMC_EHIP, "event"); break; }
-        t->ops->mc(t->stream, t->reps, a, grid, sh.wide);
+        launch_mc(t, t->stream, a, grid, sh.wide);
         if (hipEventRecord(e1, t->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             st = fail(BHMC_EHIP, "trial launch failed");
             break;
@@ -1003,6 +1024,24 @@ extern "C" bhmc_status bhmc_set_launch_shape(bhmc_tree* t, int32_t shape) {
     t->mc_wide = kShapes[shape].wide;
     t->mc_grid = std::max(1, std::min(t->R, kShapes[shape].per_cu * ncu));
     t->graph_ok = false;
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_set_moves_per_round(bhmc_tree* t, int32_t moves, int32_t* effective) {
+    if (!t) return fail(BHMC_EINVAL, "null tree");
+    if (moves < 0) return fail(BHMC_EINVAL, "moves per round must be >= 0");
+    t->moves_per_round = moves;
+    t->graph_ok = false;
+    if (effective) *effective = rounds_of(t);
+    return BHMC_OK;
+}
+
+extern "C" bhmc_status bhmc_phase_ticks(bhmc_tree* t, uint64_t* ticks, int32_t n, int32_t reset, int32_t* count) {
+    if (!t || !ticks || n < 0) return fail(BHMC_EINVAL, "bad arguments");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    const int k = t->ops->phases((unsigned long long*)ticks, n, reset);
+    if (k < 0) return fail(BHMC_EHIP, "reading the phase timers failed");
+    if (count) *count = k;
     return BHMC_OK;
 }
 

@@ -1316,6 +1316,8 @@ __global__ void __launch_bounds__(kMcBlock) k_move(Rep* reps, int r, MoveIO* io)
     }
 }
 
+#include "bhmc_moves.hpp"
+
 // Potential at every ion (targets in groups of kEnergyTargets per
 // workgroup), with the ion and its image excluded, and each ion's term of
 //   E / l_B = 1/2 q phi + 1/2 gamma a q^2 / (r^2 - a^2) + Q q / r.
@@ -1886,6 +1888,10 @@ void run_mc(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide) {
     if (wide) hipLaunchKernelGGL(k_mc<kMcBlock>, dim3(grid), dim3(kMcBlock), 0, s, reps, a);
     else hipLaunchKernelGGL(k_mc<kMcBlockBatch>, dim3(grid), dim3(kMcBlockBatch), 0, s, reps, a);
 }
+void run_mcb(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide) {
+    if (wide) hipLaunchKernelGGL(k_mcb<kMcBlock>, dim3(grid), dim3(kMcBlock), 0, s, reps, a);
+    else hipLaunchKernelGGL(k_mcb<kMcBlockBatch>, dim3(grid), dim3(kMcBlockBatch), 0, s, reps, a);
+}
 void run_move(hipStream_t s, Rep* reps, int r, MoveIO* io) {
     hipLaunchKernelGGL(k_move, dim3(1), dim3(kMcBlock), 0, s, reps, r, io);
 }
@@ -1915,7 +1921,25 @@ void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, 
                        (const double4*)w.G, (const double4*)w.Gt, dEdr, dEdq);
 }
 
-const EvalOps kOps = {run_mc, run_move, run_energy, run_grad};
+// Phase timers of the batched kernel (a build with -DBHMC_PHASE_TIMERS): ticks of the
+// constant clock per phase, then rounds and moves; reset after reading if asked.
+int read_phases(unsigned long long* out, int n, int reset) {
+#ifdef BHMC_PHASE_TIMERS
+    unsigned long long v[kNumPhases];
+    if (hipMemcpyFromSymbol(v, HIP_SYMBOL(g_phase), sizeof(v)) != hipSuccess) return -1;
+    for (int k = 0; k < n && k < kNumPhases; ++k) out[k] = v[k];
+    if (reset) {
+        for (int k = 0; k < kNumPhases; ++k) v[k] = 0;
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), v, sizeof(v)) != hipSuccess) return -1;
+    }
+    return kNumPhases;
+#else
+    (void)out; (void)n; (void)reset;
+    return 0;
+#endif
+}
+
+const EvalOps kOps = {run_mc, run_mcb, kBM, run_move, run_energy, run_grad, read_phases};
 
 }  // namespace BHMC_NS
 

@@ -22,6 +22,7 @@ struct McArgs {
     uint8_t* accept;      // per-move accept bits of a single-replica run, or null
     long long move_base;  // move index of accept[0]
     long long* sweep_add; // per replica moves added to move_end by the sweep prep kernel
+    int bm;               // batched kernel: moves per round (0 = as many as the order allows)
 };
 
 // One externally specified move (delta_energy / commit_move).
@@ -60,12 +61,17 @@ struct GradWork {
 struct EvalOps {
     // wide = 1: 512-thread workgroups (one chain); 0: 256-thread workgroups, two per CU (replicas)
     void (*mc)(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide);
+    // the same chains with several trial moves per round (N_0 = 0 only)
+    void (*mcb)(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide);
+    int moves_per_round;  // the most the batched kernel takes per round at this order
     void (*move)(hipStream_t s, Rep* reps, int r, MoveIO* io_dev);
     // max_grid > 0 bounds the number of workgroups (each then takes several target groups), so that
     // every workgroup has an HBM frontier region
     void (*energy)(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm, int max_grid);
     void (*grad)(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq,
                  double* eterm, int max_grid);
+    // phase timers of the batched Metropolis kernel: number of counters, 0 without timers
+    int (*phases)(unsigned long long* out, int n, int reset);
 };
 const EvalOps* eval_ops(int p);
 

@@ -45,6 +45,7 @@ def _brute_decisions(cells, children, members, pts, q, x, exclude, theta, p, n0,
     is opened iff N' > N_0 and it has children; otherwise every remaining
     source below it is summed directly.  Returns (phi, visited, far, near)."""
     tot = 0.0
+    stats.setdefault("farabs", 0.0)
     visited = far = near = 0
     stack = [0]
     while stack:
@@ -65,9 +66,12 @@ def _brute_decisions(cells, children, members, pts, q, x, exclude, theta, p, n0,
         if mac and npr >= n0:
             far += 1
             T = O.taylor(p, cen - x)
+            Mp = np.zeros(len(mi))
             for j in mem:
                 dd = pts[j] - cen
-                tot += q[j] * sum(T[k] * np.prod(dd ** mi[k]) for k in range(len(mi)))
+                Mp += q[j] * np.array([np.prod(dd ** mi[k]) for k in range(len(mi))])
+            tot += float(np.dot(T, Mp))
+            stats["farabs"] += float(np.sum(np.abs(T * Mp)))
         elif npr > n0 and not leaf:
             stack.extend(reversed(children[c]))
         else:
@@ -95,11 +99,14 @@ def test_n0_decision_table_by_brute_force():
         cells, children, members = _tree_tables(t, n)
         for tgt in range(0, n, 5):
             x = pts[tgt]
+            stats["farabs"] = 0.0
             ref, vis, far, near = _brute_decisions(cells, children, members, pts, q, x, {tgt}, theta, p, n0,
                                                    mi, stats)
             phi, cnt = t.phi_counts(x, exclude=[tgt])
             assert cnt.tolist() == [vis, far, near], (n0, tgt)
             assert phi == pytest.approx(ref, rel=1e-12, abs=1e-14)
+            # the far-field magnitude sum_far sum_n |T_n M'_n| the oracle reports
+            assert t.far_magnitude(x, exclude=[tgt]) == pytest.approx(stats["farabs"], rel=1e-12, abs=1e-300)
     # the boundary cases the comparisons decide were exercised
     assert stats["at_n0_internal"] > 10 and stats["far_at_n0"] > 10
 
