@@ -77,6 +77,16 @@ enum { BHMC_REASON_NONE = 0, BHMC_REASON_WALL = 1, BHMC_REASON_OVERLAP = 2 };
  *              (a move onto another ion is then rejected as an overlap).
  *   slot_slack capacity of a leaf's index array is
  *              slot_slack * max(count at build, leaf_cap) + 2.
+ *   far_fp32   1: the expansions of eq. 3.3 in the traversals of the energy,
+ *              the energy change and the Metropolis kernels use a single-
+ *              precision copy of the moments and single-precision Taylor
+ *              coefficients (eq. 3.4) per far cell, each cell's value then
+ *              added to the potential in FP64 (the energy change that feeds
+ *              the Metropolis test is accumulated in FP64; near sources, the
+ *              moments themselves and their repair stay FP64).  The rounding
+ *              this adds is at most about (C(p+3,3) + 3p + 4) 2^-24 times the
+ *              far field's magnitude sum_A sum_n |T_n M_A^n|.  The gradient is
+ *              always FP64.  0: everything in FP64.
  */
 typedef struct {
     double l_B;
@@ -95,7 +105,7 @@ typedef struct {
     double r_min, r_max;
     double hard_core;
     int32_t slot_slack;
-    int32_t _pad;
+    int32_t far_fp32;
 } bhmc_params;
 
 /* Statistics of a Monte Carlo run, summed over the moves it made. */

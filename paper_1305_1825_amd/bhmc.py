@@ -29,7 +29,7 @@ class Params(C.Structure):
         ("box_lo", C.c_double * 3), ("box_side", C.c_double),
         ("a", C.c_double), ("Q_center", C.c_double), ("eps_in", C.c_double), ("eps_out", C.c_double),
         ("r_min", C.c_double), ("r_max", C.c_double), ("hard_core", C.c_double),
-        ("slot_slack", C.c_int32), ("_pad", C.c_int32),
+        ("slot_slack", C.c_int32), ("far_fp32", C.c_int32),
     ]
 
 
@@ -119,7 +119,8 @@ def _check(st, what):
 def make_params(d: dict) -> Params:
     p = Params()
     for name, _ in Params._fields_:
-        if name == "_pad":
+        if name == "far_fp32":
+            p.far_fp32 = int(d.get("far_fp32", 0))
             continue
         if name == "box_lo":
             p.box_lo[:] = [float(v) for v in d["box_lo"]]

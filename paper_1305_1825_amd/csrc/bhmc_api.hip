@@ -204,6 +204,7 @@ static bhmc_status check_params(const bhmc_params& P, int64_t n) {
     if (P.images && !(P.a > 0.0 && P.a <= P.r_min && P.eps_in > 0.0 && P.eps_out >= 0.0))
         return fail(BHMC_EINVAL, "images need 0 < a <= r_min and eps_in > 0");
     if (!(P.hard_core >= 0.0) || !(P.l_B >= 0.0)) return fail(BHMC_EINVAL, "hard_core and l_B must be >= 0");
+    if (P.far_fp32 != 0 && P.far_fp32 != 1) return fail(BHMC_EINVAL, "far_fp32 must be 0 or 1");
     return BHMC_OK;
 }
 
@@ -226,6 +227,7 @@ static void fill_rep(Rep& r, const bhmc_params& P, int64_t n) {
         r.reach2 = reach * reach;
     }
     r.geom = P.geom; r.images = P.images; r.leaf_cap = P.leaf_cap; r.n0 = P.n0;
+    r.far32 = P.far_fp32 ? 1 : 0;
     r.max_depth = P.max_depth; r.slack = P.slot_slack;
     r.n = (int)n;
     r.nsrc = P.images ? 2 * (int)n : (int)n;
@@ -299,7 +301,7 @@ static bhmc_status alloc_phase2(bhmc_tree* t, int r) {
     const size_t nc = h.ncell, nl = h.nleaf, np = h.pool;
     size_t b = align_up(32 * nc) + align_up(16 * nc) + 4 * align_up(4 * nc) + align_up(8 * nc) +
                align_up(8 * nc * (size_t)t->mstride) + 3 * align_up(4 * nl) + align_up(32 * np) +
-               align_up(4 * np);
+               align_up(4 * np) + (h.far32 ? align_up(4 * nc * (size_t)t->mstride) : 0);
     HIP_TRY(hipMalloc(&t->arena2[r], b));
     Carver c{(char*)t->arena2[r]};
     const size_t cap_bytes = b;
@@ -310,6 +312,7 @@ static bhmc_status alloc_phase2(bhmc_tree* t, int r) {
     h.M = c.take<double>(nc * (size_t)t->mstride);
     h.lcell = c.take<int>(nl); h.lbase = c.take<int>(nl); h.lcap = c.take<int>(nl);
     h.pool4 = c.take<double4>(np); h.pidx = c.take<int>(np);
+    h.M32 = h.far32 ? c.take<float>(nc * (size_t)t->mstride) : nullptr;
     if (c.off > cap_bytes) return fail(BHMC_EINTERNAL, "tree arena carved past its allocation");
     return BHMC_OK;
 }

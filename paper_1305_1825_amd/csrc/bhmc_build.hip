@@ -402,6 +402,19 @@ k_m2m(Rep* reps, const int* rep_list, int nterms, int mstride, int level) {
     }
 }
 
+// Single-precision copy of the moments for the far field (replicas built with far32).
+__global__ void __launch_bounds__(kMomBlock)
+k_m32(Rep* reps, const int* rep_list, int nterms, int mstride) {
+    Rep& R = reps[rep_list ? rep_list[blockIdx.y] : blockIdx.y];
+    if (R.status || !R.M32) return;
+    const long long items = (long long)R.ncell * nterms;
+    for (long long it = blockIdx.x * (long long)kMomBlock + threadIdx.x; it < items;
+         it += (long long)gridDim.x * kMomBlock) {
+        const long long c = it / nterms, k = it % nterms;
+        R.M32[c * mstride + k] = (float)R.M[c * mstride + k];
+    }
+}
+
 // ------------------------------------------------------------ host launchers
 hipError_t upload_build_tables(int p, void* pinned) {
     int* mi = (int*)pinned;                        // 3 * kMaxTerms ints
@@ -459,6 +472,15 @@ void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nte
         hipLaunchKernelGGL(k_m2m, dim3(chunks(items), nrep), dim3(kMomBlock), 0, s, reps, list, nterms, mstride,
                            level);
     }
+    long long cell_items = 0;
+    bool any32 = false;
+    for (int i = 0; i < nrep; ++i) {
+        const Rep& h = host[host_list[i]];
+        cell_items = std::max(cell_items, (long long)h.ncell * nterms);
+        any32 = any32 || h.far32;
+    }
+    if (any32)
+        hipLaunchKernelGGL(k_m32, dim3(chunks(cell_items), nrep), dim3(kMomBlock), 0, s, reps, list, nterms, mstride);
 }
 
 }  // namespace bhmc

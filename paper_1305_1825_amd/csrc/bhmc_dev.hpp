@@ -35,6 +35,7 @@ struct Rep {
     double reach2;                 // (tau + 1e-12 side)^2: cells within this take the hard-core descent
     double hi[3];                  // lo + side per axis (cube walls)
     int geom, images, leaf_cap, n0, max_depth, slack;
+    int far32;                     // far field from the single-precision moments (M32)
     int n, nsrc;
     // ---- sizes (kernels)
     int ncell, nleaf, pool, depth, nsplit;
@@ -58,6 +59,7 @@ struct Rep {
     uint64_t* ckey;                // smallest key of the cell
     int* cbegin; int* cend;        // build range in the sorted order
     double* M;                     // moments, cell-major: M[cell * nterms + k]
+    float* M32;                    // single-precision copy read by the far field, or null
     int* lcell; int* lbase; int* lcap;
     double4* pool4;                // (x, y, z, q) in leaf slot order
     int* pidx;                     // source index of each slot

@@ -166,6 +166,53 @@ __device__ __forceinline__ double far_eval(double Rx, double Ry, double Rz, MP M
     return acc;
 }
 
+// The same in single precision from the single-precision moments: T_n by eq. 3.4 in
+// FP32 and sum_n T_n M^n accumulated in FP32 per cell (the caller adds the cell's value
+// to an FP64 sum).
+template <int K>
+__device__ __forceinline__ void t_step_f(float (&T)[NTERM], float Rx, float Ry, float Rz, float ir2) {
+    constexpr TEnt e = TT.e[K];
+    float f = 0.0f, g = 0.0f;
+    if constexpr (e.x1 >= 0) f = Rx * T[e.x1];
+    if constexpr (e.y1 >= 0) f = fmaf(Ry, T[e.y1], f);
+    if constexpr (e.z1 >= 0) f = fmaf(Rz, T[e.z1], f);
+    if constexpr (e.x2 >= 0) g = T[e.x2];
+    if constexpr (e.y2 >= 0) g += T[e.y2];
+    if constexpr (e.z2 >= 0) g += T[e.z2];
+    constexpr float A = (float)((2.0 * e.s - 1.0) / e.s);
+    constexpr float B = (float)((e.s - 1.0) / e.s);
+    if constexpr (e.s >= 2) T[K] = -fmaf(A, f, B * g) * ir2;
+    else T[K] = -(A * f) * ir2;
+}
+
+template <int K>
+__device__ __forceinline__ void far_rec_f(float (&T)[NTERM], float Rx, float Ry, float Rz, float ir2,
+                                          const __attribute__((address_space(1))) float* __restrict__ Mc, float& acc) {
+    if constexpr (K < NTERM) {
+        if constexpr (K > 0) t_step_f<K>(T, Rx, Ry, Rz, ir2);
+        acc = fmaf(T[K], Mc[K], acc);
+        far_rec_f<K + 1>(T, Rx, Ry, Rz, ir2, Mc, acc);
+    }
+}
+
+__device__ __forceinline__ double far_eval_f(double Rx, double Ry, double Rz, const float* M32row) {
+    const float rx = (float)Rx, ry = (float)Ry, rz = (float)Rz;
+    const float r2 = rx * rx + ry * ry + rz * rz;
+    float T[NTERM];
+    T[0] = __builtin_amdgcn_rsqf(r2);
+    T[0] = T[0] * fmaf(-0.5f * r2 * T[0], T[0], 1.5f);  // one Newton step
+    const float ir2 = T[0] * T[0];
+    float acc = 0.0f;
+    far_rec_f<0>(T, rx, ry, rz, ir2, (const __attribute__((address_space(1))) float*)M32row, acc);
+    return (double)acc;
+}
+
+// Far value of cell c at relative position R: FP32 from M32 when the replica keeps it.
+__device__ __forceinline__ double far_value(const Rep& R, int c, double Rx, double Ry, double Rz) {
+    if (R.M32) return far_eval_f(Rx, Ry, Rz, R.M32 + (size_t)c * MSTR);
+    return far_eval(Rx, Ry, Rz, grow(R.M + (size_t)c * MSTR));
+}
+
 // Polynomial sum_n C_n d^n and its gradient sum_n C_n n_k d^{n - e_k} for
 // stored coefficients C; the monomials d^n are built by the graded
 // recurrence, each from one of order |n| - 1.
@@ -259,7 +306,7 @@ __device__ __forceinline__ void far_pass(const Rep& R, Trav<NTG, BLOCK>& S, int 
         const int c = (int)(e & kCellMask), t = (int)((e >> 24) & 15u);
         if (c >= R.ncell) { S.err = kErrFarCell; continue; }
         const double4 g = R.cgeo[c];
-        add_to<NTG>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], grow(R.M + (size_t)c * MSTR)));
+        add_to<NTG>(acc, t, far_value(R, c, g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t]));
     }
     for (int j = threadIdx.x; j < nflag; j += BLOCK) {
         const uint32_t e = S.flagl[j];
@@ -592,7 +639,7 @@ __device__ __forceinline__ void far_pass_mc(const Rep& R, Trav<2, BLOCK>& S, int
         const int c = (int)(e & kCellMask);
         if (c >= R.ncell) { S.err = kErrFarCell; continue; }
         const double4 g = R.cgeo[c];
-        add_to<2>(acc, t, far_eval(g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t], grow(R.M + (size_t)c * MSTR)));
+        add_to<2>(acc, t, far_value(R, c, g.x - S.tx[t], g.y - S.ty[t], g.z - S.tz[t]));
     }
     // the cells holding an excluded source, with their corrected moments in LDS
     for (int j2 = threadIdx.x; j2 < 2 * nflag; j2 += BLOCK) {
@@ -1007,6 +1054,7 @@ __device__ __forceinline__ void commit(const Rep& R, const Trav<2, BLOCK>& S, Mc
                 if (jj & 1) { m = m + s.w * v; ++dc; } else { m = m - s.w * v; --dc; }
             }
             R.M[(size_t)c * MSTR + k] = m;
+            if (R.M32) R.M32[(size_t)c * MSTR + k] = (float)m;
             if (k == 0 && (mask & 16) && dc != 0) R.cm[c].x += dc;
         }
     }

@@ -64,11 +64,19 @@ struct BTrav {
     static constexpr int NEARCAP = 1024 + BLOCK;
     static constexpr int OVLCAP = 512;
     static constexpr int NW = BLOCK / 64;
-    uint32_t front[2][FCAP];
-    uint32_t farl[FARCAP];
-    uint32_t nearl[NEARCAP];
-    int near_base[NEARCAP];
-    int near_pre[NEARCAP + 1];
+    // the traversal's lists, free once it has ended: then per-axis power tables of the commit
+    static constexpr int LISTWORDS = 2 * FCAP + FARCAP + 3 * NEARCAP + 1;
+    static constexpr int PWROWS = (LISTWORDS / 2) / (3 * (P + 1));
+    union {
+        struct {
+            uint32_t front[2][FCAP];
+            uint32_t farl[FARCAP];
+            uint32_t nearl[NEARCAP];
+            int near_base[NEARCAP];
+            int near_pre[NEARCAP + 1];
+        };
+        double pw[PWROWS][3][P + 1];  // (x - c_x)^e, (y - c_y)^e, (z - c_z)^e of a path entry
+    };
     uint32_t flagl[4 * kBM];
     double Mx[4 * kBM][MSTR];
     uint32_t ovl[OVLCAP];
@@ -112,13 +120,22 @@ struct BMoves {
     double dE[kBM];
     // distinct cells of the accepted moves' root paths
     int nlist;
+    int pw_rows;
     int list_cell[kPathCells];
     uint32_t list_mask[kPathCells];  // bit 4 j + cc: contribution cc of move j applies
     int list_at[kPathCells];         // (j * 4 + cc) * kMaxLevels + level of its geometry; bit 30: internal
-    // scratch of the one thread that decides and moves slots: leaf count changes of the
-    // accepted moves, and the leaves touched by the round's commits (cell, base, count)
-    int dc_cell[4 * kBM], dc_val[4 * kBM];
-    int lc[4 * kBM], lb[4 * kBM], ln[4 * kBM];
+    // per pair (b, j < b): b's new position overlaps j's new one (bit j), and how committing j
+    // changes the counts of b's new ion leaf and new image leaf; per move: the energy change
+    // terms outside the traversal and whether its tracked leaves are where its keys lead
+    uint32_t ovl_new[kBM];
+    int e_ion[kBM][kBM], e_img[kBM][kBM];
+    double dE0[kBM];
+    int sane[kBM];
+    // leaf index array operations of the accepted moves: lane 4b + k, k = ion old, ion new,
+    // image old, image new; type 0 none, 1 delete, 2 append, 3 new position in place
+    int op_type[4 * kBM], op_cell[4 * kBM], op_src[4 * kBM], op_slot[4 * kBM];
+    int op_base[4 * kBM], op_count[4 * kBM];
+    int pw_row[4 * kBM];  // first power-table row of the root path of contribution (j, cc), or -1
     // trial moves drawn ahead, one per lane of the first wave
     int dr_i[kDrawBatch];
     double dr_d[kDrawBatch][4];
@@ -131,6 +148,15 @@ __device__ __forceinline__ void add_to_t(double (&acc)[NT], int t, double v) {
 #pragma unroll
     for (int k = 0; k < NT; ++k)
         if (k == t) acc[k] += v;
+}
+
+// Sum over the lanes of a wave with the same parity as this one: a lane of parity tb
+// accumulates target tb of every move (see far_pass_mb), so lanes 0 and 1 end with the
+// wave's sums for the old and the new positions.
+__device__ __forceinline__ double wave_sum_parity(double v) {
+#pragma unroll
+    for (int off = 32; off >= 2; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 // An overlap of move b's new position with source sid (an ion other than the mover,
@@ -178,61 +204,65 @@ __device__ int near_scan_mb(BTrav<BLOCK>& S, int near_n) {
     return carry;
 }
 
+// Far cells by lane pairs: the lane of parity tb evaluates target tb (old or new
+// position) of the entry's move, both lanes reading the same moment row; acc[b] of a
+// lane holds its target of move b.
 template <int BLOCK>
 __device__ __forceinline__ void far_pass_mb(const Rep& R, BTrav<BLOCK>& S, const BMoves& MV, int far_n, int nflag,
-                                            double (&acc)[kBT]) {
+                                            double (&acc)[kBM]) {
     const int tb = (int)(threadIdx.x & 1);
     for (int j2 = threadIdx.x; j2 < 2 * far_n; j2 += BLOCK) {
         const uint32_t e = S.farl[j2 >> 1];
         if (!((e >> (kOpSh + tb)) & 1u)) continue;
         const int c = (int)(e & kCellMask);
         if (c >= R.ncell) { S.err = kErrFarCell; continue; }
-        const int t = 2 * mv_of(e) + tb;
+        const int b = mv_of(e), t = 2 * b + tb;
         const double4 g = gload(R.cgeo + c);
-        add_to_t<kBT>(acc, t, far_eval(g.x - MV.tx[t], g.y - MV.ty[t], g.z - MV.tz[t], grow(R.M + (size_t)c * MSTR)));
+        add_to_t<kBM>(acc, b, far_value(R, c, g.x - MV.tx[t], g.y - MV.ty[t], g.z - MV.tz[t]));
     }
     for (int j2 = threadIdx.x; j2 < 2 * nflag; j2 += BLOCK) {
         const uint32_t e = S.flagl[j2 >> 1];
         if (!((e >> (kOpSh + tb)) & 1u)) continue;
         const int c = (int)(e & kCellMask);
         if (c >= R.ncell) { S.err = kErrFarCell; continue; }
-        const int t = 2 * mv_of(e) + tb;
+        const int b = mv_of(e), t = 2 * b + tb;
         const double4 g = gload(R.cgeo + c);
-        add_to_t<kBT>(acc, t, far_eval(g.x - MV.tx[t], g.y - MV.ty[t], g.z - MV.tz[t], lrow(S.Mx[j2 >> 1])));
+        add_to_t<kBM>(acc, b, far_eval(g.x - MV.tx[t], g.y - MV.ty[t], g.z - MV.tz[t], lrow(S.Mx[j2 >> 1])));
     }
 }
 
+// Near leaves by lane pairs as the far cells: slot f of the flattened near leaves is
+// taken by lanes 2f (old position) and 2f + 1 (new position); for the new position,
+// every ion other than the mover within tau is an overlap.
 template <int BLOCK>
 __device__ __forceinline__ void near_pass_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int near_n, int total,
-                                             double (&acc)[kBT]) {
+                                             double (&acc)[kBM]) {
     const int n_ion = R.n;
-    for (int f = threadIdx.x; f < total; f += BLOCK) {
+    const int tb = (int)(threadIdx.x & 1);
+    for (int f2 = threadIdx.x; f2 < 2 * total; f2 += BLOCK) {
+        const int f = f2 >> 1;
         int lo = 0, hi = near_n - 1;  // last j with near_pre[j] <= f
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (S.near_pre[mid] <= f) lo = mid; else hi = mid - 1;
         }
         const uint32_t e = S.nearl[lo];
+        if (!((e >> (kOpSh + tb)) & 1u)) continue;
         const int b = mv_of(e);
-        const uint32_t mask = (e >> kOpSh) & 3u;
         const int slot = S.near_base[lo] + (f - S.near_pre[lo]);
         const double4 s = gload(R.pool4 + slot);
         const int sid = gload(R.pidx + slot);
         const int ion = MV.ion[b];
         if (((e & kMbIon) && sid == ion) || ((e & kMbImg) && sid == n_ion + ion)) continue;
-#pragma unroll
-        for (int tb = 0; tb < 2; ++tb) {
-            if (!((mask >> tb) & 1u)) continue;
-            const int t = 2 * b + tb;
-            const double dx = MV.tx[t] - s.x, dy = MV.ty[t] - s.y, dz = MV.tz[t] - s.z;
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            if (tb == 1 && sid < n_ion && sid != ion && d2 <= R.tau2) record_overlap(MV, b, sid, n_ion);
-            if (d2 == 0.0) {
-                if (!(tb == 1 && sid < n_ion)) record_overlap(MV, b, sid, n_ion);
-                continue;
-            }
-            add_to_t<kBT>(acc, t, s.w * rsqrt_nr(d2));
+        const int t = 2 * b + tb;
+        const double dx = MV.tx[t] - s.x, dy = MV.ty[t] - s.y, dz = MV.tz[t] - s.z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (tb == 1 && sid < n_ion && sid != ion && d2 <= R.tau2) record_overlap(MV, b, sid, n_ion);
+        if (d2 == 0.0) {
+            if (!(tb == 1 && sid < n_ion)) record_overlap(MV, b, sid, n_ion);
+            continue;
         }
+        add_to_t<kBM>(acc, b, s.w * rsqrt_nr(d2));
     }
 }
 
@@ -292,9 +322,9 @@ __device__ void traverse_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, Hook&& ho
     using TS = BTrav<BLOCK>;
     constexpr int NW = TS::NW;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    double acc[kBT];
+    double acc[kBM];  // this lane's target (its parity) of every move
 #pragma unroll
-    for (int k = 0; k < kBT; ++k) acc[k] = 0.0;
+    for (int k = 0; k < kBM; ++k) acc[k] = 0.0;
     int cur = 0, fs = MV.fs0, far_n = 0, near_n = 0, nflag = 0, buf = 0;
     bool failed = false, frontier_full = false;
     uint32_t* const gfr = spill_region(R);
@@ -442,9 +472,9 @@ __device__ void traverse_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, Hook&& ho
 #endif
     near_pass_mb<BLOCK>(R, S, MV, near_n, total, acc);
 #pragma unroll
-    for (int k = 0; k < kBT; ++k) {
-        const double sum = wave_sum(acc[k]);
-        if (lane == 0) S.red[w][k] = sum;
+    for (int k = 0; k < kBM; ++k) {
+        const double sum = wave_sum_parity(acc[k]);
+        if (lane < 2) S.red[w][2 * k + lane] = sum;
     }
     __syncthreads();
     PHASE(kPhNear);
@@ -523,90 +553,6 @@ __device__ __forceinline__ void prefetch_stage_mb(const Rep& R, BMoves& MV, int 
     }
 }
 
-// Leaf index arrays of the accepted moves of the round, in move order (Sec. 3.3):
-// one thread.  Leaves touched earlier in the round are followed in lc / lb / ln, and
-// a slot or last entry of such a leaf is read again from memory (this thread wrote it).
-__device__ void commit_slots_mb(const Rep& R, BMoves& MV) {
-    const bool imgs = R.images != 0;
-    int* const lc = MV.lc;
-    int* const lb = MV.lb;
-    int* const ln = MV.ln;
-    int nl = 0;
-    auto find = [&](int cell, int base, int count, bool& seen) {
-        for (int k = 0; k < nl; ++k)
-            if (lc[k] == cell) { seen = true; return k; }
-        seen = false;
-        lc[nl] = cell; lb[nl] = base; ln[nl] = count;
-        return nl++;
-    };
-    for (int b = 0; b < MV.ndone; ++b) {
-        if (!MV.acc[b]) continue;
-        const int i = MV.ion[b], K = R.n + i;
-        bool seen_a, seen_b;
-        const int a = find(MV.tr[b][0].x, MV.lm_old[b][0].z, MV.lm_old[b][0].x, seen_a);
-        const int bb = find(MV.path[b][1][MV.plen[b][1] - 1], MV.lm_new[b][0].z, MV.lm_new[b][0].x, seen_b);
-        int img_slot = imgs ? MV.tr[b][1].y : -1;
-        const double4 ion_new = MV.ct[b][1];
-        const int k = seen_a ? R.track[i].y : MV.tr[b][0].y;
-        if (a != bb) {
-            const int last = ln[a] - 1;
-            int moved;
-            double4 mv;
-            if (!seen_a) { moved = MV.last_pidx[b][0]; mv = MV.last_pool[b][0]; }
-            else { moved = R.pidx[lb[a] + last]; mv = R.pool4[lb[a] + last]; }
-            if (k != last) {
-                R.pool4[lb[a] + k] = mv;
-                R.pidx[lb[a] + k] = moved;
-                if (moved >= 0 && moved < R.nsrc) R.track[moved] = make_int2(lc[a], k);
-                else MV.err = kErrCommitSource;
-                if (moved == K) img_slot = k;
-            }
-            ln[a] = last;
-            R.cm[lc[a]].x = last;
-            const int pos = ln[bb];
-            R.pool4[lb[bb] + pos] = ion_new;
-            R.pidx[lb[bb] + pos] = i;
-            R.track[i] = make_int2(lc[bb], pos);
-            ln[bb] = pos + 1;
-            R.cm[lc[bb]].x = pos + 1;
-        } else {
-            R.pool4[lb[a] + k] = ion_new;
-        }
-        R.src[i] = ion_new;
-        if (imgs) {
-            bool seen_c, seen_d;
-            const int cc = find(MV.tr[b][1].x, MV.lm_old[b][1].z, MV.lm_old[b][1].x, seen_c);
-            const int dd = find(MV.path[b][3][MV.plen[b][3] - 1], MV.lm_new[b][1].z, MV.lm_new[b][1].x, seen_d);
-            if (seen_c) img_slot = R.track[K].y;  // written by this thread if it changed
-            const double4 img_new = MV.ct[b][3];
-            if (cc != dd) {
-                const int last = ln[cc] - 1;
-                int moved;
-                double4 mv;
-                if (!seen_c) { moved = MV.last_pidx[b][1]; mv = MV.last_pool[b][1]; }
-                else { moved = R.pidx[lb[cc] + last]; mv = R.pool4[lb[cc] + last]; }
-                if (img_slot != last) {
-                    R.pool4[lb[cc] + img_slot] = mv;
-                    R.pidx[lb[cc] + img_slot] = moved;
-                    if (moved >= 0 && moved < R.nsrc) R.track[moved] = make_int2(lc[cc], img_slot);
-                    else MV.err = kErrCommitSource;
-                }
-                ln[cc] = last;
-                R.cm[lc[cc]].x = last;
-                const int pos = ln[dd];
-                R.pool4[lb[dd] + pos] = img_new;
-                R.pidx[lb[dd] + pos] = K;
-                R.track[K] = make_int2(lc[dd], pos);
-                ln[dd] = pos + 1;
-                R.cm[lc[dd]].x = pos + 1;
-            } else {
-                R.pool4[lb[cc] + img_slot] = img_new;
-            }
-            R.src[K] = img_new;
-        }
-    }
-}
-
 // One round of up to nb moves (draws b0 .. b0 + nb - 1 of MV's batch, move indices
 // m .. m + nb - 1).  Returns the number of moves consumed and a stop status.
 template <int BLOCK>
@@ -638,6 +584,7 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
             MV.tx[2 * b + 1] = rx; MV.ty[2 * b + 1] = ry; MV.tz[2 * b + 1] = rz;
             MV.ovl_fixed[b] = 0;
             MV.ovl_moved[b] = 0u;
+            MV.ovl_new[b] = 0u;
             MV.acc[b] = 0;
             MV.reason[b] = 0;
         }
@@ -732,8 +679,11 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
         __syncthreads();
         return o;
     }
-    // ---- corrections: thread (j, b, t), j < b, sums what move j's four contributions add to
-    // target t of move b once j is committed
+    // ---- in parallel (threads 0-127, 128-191, 192-199): corrections (thread (j, b, t), j < b: what move j's four contributions add
+    // to target t of move b once j is committed); for every pair, whether b's new position
+    // overlaps j's and how j changes the counts of b's new leaves; for every move, its energy
+    // change on the start-of-round tree and whether its tracked leaves are the ones its keys
+    // lead to
     if (tid < 2 * nb * nb) {
         const int j = tid / (2 * nb), b = (tid >> 1) % nb, tb = tid & 1;
         if (j < b && !MV.wall[j] && !MV.wall[b]) {
@@ -746,76 +696,157 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
             }
             MV.corr[j][b][tb] = v;
         }
-    }
-    __syncthreads();
-    PHASE(kPhCorr);
-    // ---- decisions, in move order
-    if (tid == 0) {
-        uint32_t acc_mask = 0;
-        int* const dc_cell = MV.dc_cell;  // leaf count changes of the accepted moves
-        int* const dc_val = MV.dc_val;
-        int ndc = 0;
-        auto count_of = [&](int cell, int base_count) {
-            int v = base_count;
-            for (int k = 0; k < ndc; ++k)
-                if (dc_cell[k] == cell) v += dc_val[k];
-            return v;
-        };
-        auto add_dc = [&](int cell, int d) {
-            for (int k = 0; k < ndc; ++k)
-                if (dc_cell[k] == cell) { dc_val[k] += d; return; }
-            dc_cell[ndc] = cell; dc_val[ndc] = d; ++ndc;
-        };
-        int done = nb;
-        for (int b = 0; b < nb; ++b) {
-            MV.dE[b] = kInf;
-            if (MV.wall[b]) { MV.reason[b] = 1; continue; }
-            bool ovl = MV.ovl_fixed[b] != 0 || (MV.ovl_moved[b] & ~acc_mask) != 0u;
+    } else if (tid >= 128 && tid < 128 + nb * nb) {
+        const int j = (tid - 128) / nb, b = (tid - 128) % nb;
+        if (j < b && !MV.wall[j] && !MV.wall[b]) {
+            const double4 sn = MV.ct[b][1], s = MV.ct[j][1];
+            const double dx = sn.x - s.x, dy = sn.y - s.y, dz = sn.z - s.z;
+            if (dx * dx + dy * dy + dz * dz <= R.tau2) atomicOr(&MV.ovl_new[b], 1u << j);
+            // leaves of the moves: ion old / new, image old / new
+            const int cio = MV.tr[j][0].x, cin = MV.path[j][1][MV.plen[j][1] - 1];
+            const int cmo = imgs ? MV.tr[j][1].x : -1, cmn = imgs ? MV.path[j][3][MV.plen[j][3] - 1] : -1;
+            const int bin = MV.path[b][1][MV.plen[b][1] - 1];
+            const int bmn = imgs ? MV.path[b][3][MV.plen[b][3] - 1] : -2;
+            int ei = 0, em = 0;
+            if (cin != cio) { ei += (cin == bin) - (cio == bin); em += (cin == bmn) - (cio == bmn); }
+            if (imgs && cmn != cmo) { ei += (cmn == bin) - (cmo == bin); em += (cmn == bmn) - (cmo == bmn); }
+            MV.e_ion[b][j] = ei;
+            MV.e_img[b][j] = em;
+        }
+    } else if (tid >= 192 && tid < 192 + nb) {
+        const int b = tid - 192;
+        if (!MV.wall[b]) {
             const double4 sn = MV.ct[b][1], so = MV.ct[b][0];
-            for (int j = 0; j < b && !ovl; ++j) {
-                if (!((acc_mask >> j) & 1u)) continue;
-                const double4 s = MV.ct[j][1];
-                const double dx = sn.x - s.x, dy = sn.y - s.y, dz = sn.z - s.z;
-                if (dx * dx + dy * dy + dz * dz <= R.tau2) ovl = true;
-            }
-            if (ovl) { MV.reason[b] = 2; continue; }
-            double pn = MV.pot[2 * b + 1], po = MV.pot[2 * b];
-            for (int j = 0; j < b; ++j)
-                if ((acc_mask >> j) & 1u) { pn += MV.corr[j][b][1]; po += MV.corr[j][b][0]; }
             const double q = so.w, l = R.l_B;
-            double dE = l * q * (pn - po);
+            double d0 = 0.0;  // the exact self-image and central-charge changes
             if (R.geom == 1) {
                 const double rn2 = sn.x * sn.x + sn.y * sn.y + sn.z * sn.z;
                 const double ro2 = so.x * so.x + so.y * so.y + so.z * so.z;
-                if (imgs) dE += 0.5 * l * R.gamma * R.a * q * q * (1.0 / (rn2 - R.a2) - 1.0 / (ro2 - R.a2));
-                if (R.Qc != 0.0) dE += l * R.Qc * q * (1.0 / sqrt(rn2) - 1.0 / sqrt(ro2));
+                if (imgs) d0 += 0.5 * l * R.gamma * R.a * q * q * (1.0 / (rn2 - R.a2) - 1.0 / (ro2 - R.a2));
+                if (R.Qc != 0.0) d0 += l * R.Qc * q * (1.0 / sqrt(rn2) - 1.0 / sqrt(ro2));
             }
-            MV.dE[b] = dE;
-            if (!(dE <= 0.0 || MV.alpha[b] <= exp(-dE))) continue;
-            // the tracked leaves must be the leaves the old positions' keys lead to
+            MV.dE0[b] = d0;
             bool sane = MV.tr[b][0].x == MV.path[b][0][MV.plen[b][0] - 1];
             if (imgs) sane = sane && MV.tr[b][1].x == MV.path[b][2][MV.plen[b][2] - 1];
-            if (!sane) { MV.err = kErrCommitSlot; done = b; break; }
-            // would a leaf index array overflow?
-            const int cio = MV.tr[b][0].x, cin = MV.path[b][1][MV.plen[b][1] - 1];
-            bool ok = true;
-            if (cin != cio && count_of(cin, MV.lm_new[b][0].x) + 1 > MV.lm_new[b][0].w) ok = false;
-            int cmo = -1, cmn = -1;
-            if (imgs) {
-                cmo = MV.tr[b][1].x; cmn = MV.path[b][3][MV.plen[b][3] - 1];
-                if (cmn != cmo) {
-                    int c = count_of(cmn, MV.lm_new[b][1].x);
-                    if (cin != cio) { if (cmn == cin) c += 1; if (cmn == cio) c -= 1; }
-                    if (c + 1 > MV.lm_new[b][1].w) ok = false;
+            MV.sane[b] = sane ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    PHASE(kPhCorr);
+    // ---- decisions, in move order, by the first wave.  Everything the loop reads is first
+    // brought into registers at once: lane b holds move b's own data, lane j its part of the
+    // sums of every later move; the loop then only shuffles.
+    if (tid < 64) {
+        const int lane = tid;
+        double cr0[kBM], cr1[kBM];
+        int ei_r[kBM], em_r[kBM];
+#pragma unroll
+        for (int b = 0; b < kBM; ++b) {
+            const bool v = lane < b && b < nb;
+            cr0[b] = v ? MV.corr[lane][b][0] : 0.0;
+            cr1[b] = v ? MV.corr[lane][b][1] : 0.0;
+            ei_r[b] = v ? MV.e_ion[b][lane] : 0;
+            em_r[b] = v ? MV.e_img[b][lane] : 0;
+        }
+        const bool mine = lane < nb;
+        const int my_wall = mine ? MV.wall[lane] : 1;
+        const int my_fixed = mine ? MV.ovl_fixed[lane] : 0;
+        const uint32_t my_moved = mine ? MV.ovl_moved[lane] : 0u, my_new = mine ? MV.ovl_new[lane] : 0u;
+        const double my_pn = mine ? MV.pot[2 * lane + 1] : 0.0, my_po = mine ? MV.pot[2 * lane] : 0.0;
+        const double my_q = mine ? MV.ct[lane][0].w : 0.0, my_d0 = mine ? MV.dE0[lane] : 0.0;
+        const double my_alpha = mine ? MV.alpha[lane] : 0.0;
+        const int my_sane = mine ? MV.sane[lane] : 0;
+        const int my_cio = mine ? MV.tr[lane][0].x : -1;
+        const int my_cin = mine ? MV.path[lane][1][MV.plen[lane][1] - 1] : -1;
+        const int my_cmo = (mine && imgs) ? MV.tr[lane][1].x : -1;
+        const int my_cmn = (mine && imgs) ? MV.path[lane][3][MV.plen[lane][3] - 1] : -1;
+        const int4 my_l0 = mine ? MV.lm_new[lane][0] : make_int4(0, 0, 0, 0);
+        const int4 my_l1 = (mine && imgs) ? MV.lm_new[lane][1] : make_int4(0, 0, 0, 0);
+        uint32_t acc_mask = 0;
+        int done = nb, stop = 0, err = 0;
+        int my_reason = 0, my_acc = 0;
+        double my_dE = kInf;
+        bool ended = false;
+#pragma unroll
+        for (int b = 0; b < kBM; ++b) {
+            if (b >= nb || ended) continue;  // uniform
+            int reason = 0;
+            double dE = kInf;
+            bool accept = false;
+            const int wall = __shfl(my_wall, b, 64);
+            const int fixed = __shfl(my_fixed, b, 64);
+            const uint32_t moved = (uint32_t)__shfl((int)my_moved, b, 64);
+            const uint32_t nw = (uint32_t)__shfl((int)my_new, b, 64);
+            if (wall) {
+                reason = 1;
+            } else if (fixed != 0 || (moved & ~acc_mask) != 0u || (nw & acc_mask) != 0u) {
+                reason = 2;
+            } else {
+                const bool on = lane < kBM && ((acc_mask >> lane) & 1u);  // only lanes j < b can be set
+                double c1 = on ? cr1[b] : 0.0, c0 = on ? cr0[b] : 0.0;
+                int ei = on ? ei_r[b] : 0, em = on ? em_r[b] : 0;
+#pragma unroll
+                for (int off = 4; off >= 1; off >>= 1) {  // the moves sit in the first 8 lanes
+                    c1 += __shfl_xor(c1, off, 64);
+                    c0 += __shfl_xor(c0, off, 64);
+                    ei += __shfl_xor(ei, off, 64);
+                    em += __shfl_xor(em, off, 64);
+                }
+                c1 = __shfl(c1, 0, 64); c0 = __shfl(c0, 0, 64);
+                ei = __shfl(ei, 0, 64); em = __shfl(em, 0, 64);
+                const double pn = __shfl(my_pn, b, 64) + c1, po = __shfl(my_po, b, 64) + c0;
+                dE = R.l_B * __shfl(my_q, b, 64) * (pn - po) + __shfl(my_d0, b, 64);
+                accept = dE <= 0.0 || __shfl(my_alpha, b, 64) <= exp(-dE);
+                if (accept) {
+                    if (!__shfl(my_sane, b, 64)) { err = kErrCommitSlot; done = b; ended = true; continue; }
+                    // would a leaf index array overflow?
+                    const int cio = __shfl(my_cio, b, 64), cin = __shfl(my_cin, b, 64);
+                    bool ok = !(cin != cio && __shfl(my_l0.x, b, 64) + ei + 1 > __shfl(my_l0.w, b, 64));
+                    if (imgs) {
+                        const int cmo = __shfl(my_cmo, b, 64), cmn = __shfl(my_cmn, b, 64);
+                        if (cmn != cmo) {
+                            int c = __shfl(my_l1.x, b, 64) + em;
+                            if (cin != cio) { if (cmn == cin) c += 1; if (cmn == cio) c -= 1; }
+                            if (c + 1 > __shfl(my_l1.w, b, 64)) ok = false;
+                        }
+                    }
+                    if (!ok) { stop = -6; done = b; ended = true; continue; }
+                    acc_mask |= 1u << b;
                 }
             }
-            if (!ok) { MV.stop = -6; done = b; break; }
-            if (cin != cio) { add_dc(cio, -1); add_dc(cin, 1); }
-            if (imgs && cmn != cmo) { add_dc(cmo, -1); add_dc(cmn, 1); }
-            MV.acc[b] = 1;
-            acc_mask |= 1u << b;
+            if (lane == b) { my_reason = reason; my_dE = dE; my_acc = accept ? 1 : 0; }
         }
-        MV.ndone = done;
+        if (mine) {
+            MV.reason[lane] = my_reason;
+            MV.dE[lane] = my_dE;
+            MV.acc[lane] = (lane < done) ? my_acc : 0;
+        }
+        if (lane == 0) { MV.ndone = done; MV.stop = stop; MV.err = err; }
+        // the leaf index array operations of the accepted moves: lane 4b + k, k = ion old, ion new,
+        // image old, image new (in this order, the order of the move-by-move commit)
+        if (lane < 4 * kBM) {
+            const int b = lane >> 2, k = lane & 3;
+            int type = 0, cell = -1, src = -1, slot0 = -1;
+            int4 hdr = make_int4(0, 0, 0, 0);
+            if (b < done && ((acc_mask >> b) & 1u) && (k < 2 || imgs)) {
+                const int j = k >> 1;  // 0: the ion, 1: the image
+                const int c_old = MV.tr[b][j].x, c_new = MV.path[b][2 * j + 1][MV.plen[b][2 * j + 1] - 1];
+                src = j == 0 ? MV.ion[b] : R.n + MV.ion[b];
+                if (c_old == c_new) {
+                    if ((k & 1) == 0) { type = 3; cell = c_old; hdr = MV.lm_old[b][j]; slot0 = MV.tr[b][j].y; }
+                } else if ((k & 1) == 0) {
+                    type = 1; cell = c_old; hdr = MV.lm_old[b][j]; slot0 = MV.tr[b][j].y;
+                } else {
+                    type = 2; cell = c_new; hdr = MV.lm_new[b][j];
+                }
+            }
+            MV.op_type[lane] = type;
+            MV.op_cell[lane] = cell;
+            MV.op_src[lane] = src;
+            MV.op_slot[lane] = slot0;
+            MV.op_base[lane] = hdr.z;
+            MV.op_count[lane] = hdr.x;
+        }
     }
     __syncthreads();
     PHASE(kPhDecide);
@@ -825,7 +856,60 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
         return o;
     }
     const int ndone = MV.ndone;
-    // ---- distinct cells of the accepted moves' root paths, in (move, contribution) order
+    // ---- leaf index arrays (Sec. 3.3: delete = the last entry fills the hole, add = append), one
+    // lane per leaf taking that leaf's operations in order; moves between leaves are independent.
+    // A source that fills a hole and leaves the leaf later in the round has its slot followed in
+    // op_slot; its final tracking is written by the lane of the leaf it moves to.
+    if (tid < 4 * kBM) {
+        const int o = tid;
+        const int cell = MV.op_cell[o];
+        bool lead = MV.op_type[o] != 0;
+        for (int o2 = 0; o2 < o && lead; ++o2)
+            if (MV.op_type[o2] != 0 && MV.op_cell[o2] == cell) lead = false;
+        if (lead) {
+            const int base = MV.op_base[o];
+            int count = MV.op_count[o];
+            for (int o2 = o; o2 < 4 * kBM; ++o2) {
+                const int type = MV.op_type[o2];
+                if (type == 0 || MV.op_cell[o2] != cell) continue;
+                const int src = MV.op_src[o2];
+                const double4 nv = MV.ct[o2 >> 2][(o2 & 3) == 0 || (o2 & 3) == 1 ? 1 : 3];
+                if (type == 2) {  // append
+                    R.pool4[base + count] = nv;
+                    R.pidx[base + count] = src;
+                    R.track[src] = make_int2(cell, count);
+                    ++count;
+                } else {
+                    const int k = MV.op_slot[o2];
+                    if (type == 3) {  // the source stays in this leaf: new position in place
+                        R.pool4[base + k] = nv;
+                    } else {          // delete: the last entry fills the hole
+                        const int last = count - 1;
+                        if (k != last) {
+                            const int moved = R.pidx[base + last];
+                            const double4 mv = R.pool4[base + last];
+                            R.pool4[base + k] = mv;
+                            R.pidx[base + k] = moved;
+                            bool leaves_later = false;
+                            for (int o3 = o2 + 1; o3 < 4 * kBM; ++o3)
+                                if (MV.op_cell[o3] == cell && (MV.op_type[o3] == 1 || MV.op_type[o3] == 3) &&
+                                    MV.op_src[o3] == moved) {
+                                    MV.op_slot[o3] = k;
+                                    leaves_later = MV.op_type[o3] == 1;
+                                }
+                            if (moved < 0 || moved >= R.nsrc) MV.err = kErrCommitSource;
+                            else if (!leaves_later) R.track[moved] = make_int2(cell, k);
+                        }
+                        count = last;
+                    }
+                }
+                if (type != 1) R.src[src] = nv;
+            }
+            R.cm[cell].x = count;
+        }
+    }
+    // ---- meanwhile: distinct cells of the accepted moves' root paths, in (move, contribution)
+    // order, each with the contributions that apply to it
     for (int it = tid; it < ndone * 4 * kMaxLevels; it += BLOCK) {
         const int j = it / (4 * kMaxLevels), cc = (it / kMaxLevels) & 3, l = it % kMaxLevels;
         if (!MV.acc[j] || cc >= nps || l >= MV.plen[j][cc]) continue;
@@ -849,10 +933,37 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
         MV.list_mask[slot] = mask;
         MV.list_at[slot] = ((j * 4 + cc) * kMaxLevels + l) | (l < MV.plen[j][cc] - 1 ? (1 << 30) : 0);
     }
-    if (tid == BLOCK - 1) commit_slots_mb(R, MV);
     __syncthreads();
     PHASE(kPhSlots);
-    // ---- moments and counts of the distinct path cells, contributions in move order
+    // ---- moments and counts of the distinct path cells, contributions in move order.  The powers
+    // of each path entry's offset from its cell centre are tabulated first (in the traversal's
+    // list space), so a term is three table reads per contribution; without room, d^n is
+    // formed by repeated multiplication.
+    if (tid == 0) {
+        int rows = 0;
+        for (int jc = 0; jc < 4 * kBM; ++jc) {
+            const int j = jc >> 2, cc = jc & 3;
+            if (j < ndone && MV.acc[j] && cc < nps) { MV.pw_row[jc] = rows; rows += MV.plen[j][cc]; }
+            else MV.pw_row[jc] = -1;
+        }
+        MV.pw_rows = rows;
+    }
+    __syncthreads();
+    const bool use_pw = MV.pw_rows <= BTrav<BLOCK>::PWROWS;
+    if (use_pw) {
+        for (int it = tid; it < 4 * kBM * kMaxLevels * 3; it += BLOCK) {
+            const int jc = it / (kMaxLevels * 3), l = (it / 3) % kMaxLevels, ax = it % 3;
+            const int j = jc >> 2, cc = jc & 3;
+            if (MV.pw_row[jc] < 0 || l >= MV.plen[j][cc]) continue;
+            const double4 sc = MV.ct[j][cc], g = MV.path_geo[j][cc][l];
+            const double d = ax == 0 ? sc.x - g.x : (ax == 1 ? sc.y - g.y : sc.z - g.z);
+            double* row = S.pw[MV.pw_row[jc] + l][ax];
+            double v = 1.0;
+            row[0] = 1.0;
+            for (int e = 1; e <= P; ++e) { v *= d; row[e] = v; }
+        }
+        __syncthreads();
+    }
     const int items = MV.nlist * NTERM;
     constexpr int G = 4;
     for (int base = tid; base < items; base += G * BLOCK) {
@@ -869,18 +980,26 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
             const int li = it / NTERM, k = it % NTERM;
             const int c = MV.list_cell[li];
             const int at = MV.list_at[li];
-            const int aj = (at & ((1 << 30) - 1)) / kMaxLevels, al = (at & ((1 << 30) - 1)) % kMaxLevels;
-            const double4 g = MV.path_geo[aj >> 2][aj & 3][al];
+            const int l = (at & ((1 << 30) - 1)) % kMaxLevels;
             const uint32_t code = S.mi[k];
+            const int n1 = (int)(code & 255u), n2 = (int)((code >> 8) & 255u), n3 = (int)(code >> 16);
             double m = mk[u];
             int dc = 0;
             for (uint32_t rest = MV.list_mask[li]; rest; rest &= rest - 1u) {
                 const int bit = __builtin_ctz(rest);
-                const double4 s = MV.ct[bit >> 2][bit & 3];
-                const double v = mono(code, s.x - g.x, s.y - g.y, s.z - g.z);
-                if (bit & 1) { m = m + s.w * v; ++dc; } else { m = m - s.w * v; --dc; }
+                const double4 sc = MV.ct[bit >> 2][bit & 3];
+                double v;
+                if (use_pw) {
+                    const int row = MV.pw_row[bit] + l;
+                    v = S.pw[row][0][n1] * S.pw[row][1][n2] * S.pw[row][2][n3];
+                } else {
+                    const double4 g = MV.path_geo[bit >> 2][bit & 3][l];
+                    v = mono(code, sc.x - g.x, sc.y - g.y, sc.z - g.z);
+                }
+                if (bit & 1) { m = m + sc.w * v; ++dc; } else { m = m - sc.w * v; --dc; }
             }
             R.M[(size_t)c * MSTR + k] = m;
+            if (R.M32) R.M32[(size_t)c * MSTR + k] = (float)m;
             if (k == 0 && (at & (1 << 30)) && dc != 0) R.cm[c].x += dc;
         }
     }
