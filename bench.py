@@ -65,6 +65,15 @@ def traffic(kind, units):
     return t[kind]["bytes"]
 
 
+def kernel_label(tune, p):
+    """The Metropolis kernel an autotuned handle launches: one trial move per traversal (k_mc)
+    or rounds of several (k_mcb), 512- or 256-thread workgroups."""
+    mpr = tune.get("moves_per_round", 1)
+    width = 512 if tune.get("shape_index", 0) == 0 else 256
+    name = "k_mc<%d>" % width if mpr == 1 else "k_mcb<%d>" % width
+    return "%s (p=%d, %s, %d trial move%s per traversal)" % (name, p, tune.get("shape", ""), mpr, "" if mpr == 1 else "s")
+
+
 def log(*a):
     print("bench:", *a, file=sys.stderr, flush=True)
 
@@ -155,11 +164,13 @@ def run_plain(c, steps, warmup, tune=True, moves_per_round=0):
     def one_step(timed):
         nonlocal last, final
         t = bhmc.Tree(P, x, y, z, q)
-        shape["moves_per_round"] = t.set_moves_per_round(moves_per_round)
-        if tune and "choice" not in shape:  # the first step picks the launch shape, later steps reuse it
+        if tune and "choice" not in shape:  # the first step picks shape and tile, later steps reuse them
             shape.update(t.autotune(seed=c["seed"], step=c["step"], trial_moves=1000))
         elif "choice" in shape:
-            t.set_shape(shape["choice"])
+            t.set_shape(shape["shape_index"])
+            t.set_moves_per_round(shape["moves_per_round"])
+        else:
+            shape["moves_per_round"] = t.set_moves_per_round(moves_per_round)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
@@ -415,6 +426,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--no-stated", action="store_true", help="skip the theta=0.5, p=6 leg")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB once with a plain device copy (the reference dispatch of the "
+                         "HBM counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -423,6 +437,15 @@ def main():
     import torch
     from paper_1305_1825_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read and %d written" % (src.numel() * 8, src.numel() * 8))
+        del src, dst
+        torch.cuda.empty_cache()
     log("copy probe")
     probe = copy_probe()
     achievable = probe["gbs"]
@@ -455,7 +478,8 @@ def main():
         "config": {"workload": "colloid a=10 Q=-50 eps 2/80, N=10000 ions + 10000 Kelvin images, "
                                "shell 10.5<r<40, hard core 0.5, theta=%.1f, p=%d, N_0=%d, leaf 16, "
                                "%d trial moves per step (build included)" % (g["theta"], g["p"], g["n0"], c["moves"]),
-                   "chain": "plain single chain", "seed": c["seed"]},
+                   "chain": "one chain, trial moves evaluated in rounds of up to 8 and decided in order",
+                   "seed": c["seed"]},
         "stats": res["stats"],
         "autotune": res["autotune"],
         "mc_kernel_ms_per_step": mc_ms,
@@ -464,7 +488,7 @@ def main():
                      "achievable": achievable, "frac_achievable": achieved / achievable,
                      "per_cu": {"peak": CU_L2_GBS, "frac": achieved / CU_L2_GBS,
                                 "note": "one workgroup on one CU: bytes through that CU over its L2 path"},
-                     "kernel": "k_mcb<512> (p=%d, rounds of %d trial moves)" % (g["p"], res["autotune"].get("moves_per_round", 1)),
+                     "kernel": kernel_label(res["autotune"], g["p"]),
                      "algorithmic_bytes_per_move": ab["per_move"],
                      "per_move_counts": {k: ab[k] for k in ("visited", "far", "near", "eval_fraction")}},
         "copy_probe": probe,
@@ -496,7 +520,7 @@ def main():
         b["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "achievable": achievable, "frac_achievable": ach / achievable,
                          "traffic": traffic("sweep", b["moves"] // b["sweeps"]),
-                         "kernel": "k_mc (p=%d), one sweep per launch" % GATED_REPLICAS["p"],
+                         "kernel": kernel_label(b["autotune"], GATED_REPLICAS["p"]) + ", one sweep per launch",
                          "algorithmic_bytes_per_move": bpm}
         b["ratio_vs_headline_chain"] = b["moves_per_s"] / value
         out["batched"] = b

@@ -224,23 +224,29 @@ bhmc_status bhmc_mc_run(bhmc_tree* tree, int32_t replica, uint64_t seed, uint64_
 bhmc_status bhmc_batch_sweep(bhmc_tree* tree, uint64_t seed, int32_t n_sweeps, double step,
                              int32_t use_graph, bhmc_stats* stats_host);
 
-/* Autotuner of the replica kernel's launch shape.  Times trial_moves moves
- * (at most N_r) of every replica with each candidate shape -- 0: 512-thread
- * workgroups, one per CU; 1: 256-thread workgroups, one per CU; 2:
- * 256-thread workgroups, two per CU -- rebuilding every replica from its
- * built positions after each trial, and keeps the fastest for the handle's
- * later bhmc_mc_run and bhmc_batch_sweep calls.  Needs the replicas as built
- * (no moves run yet; EINVAL otherwise) and leaves them exactly as built.
- * choice (nullable, host): the shape kept; ms_host (nullable, host, 3
- * floats): each shape's trial time (0 if not tried: a one-replica handle
- * tries shapes 0 and 1).  The chain of a replica depends on the shape only
- * through the rounding of its energy sums. */
+/* Autotuner of the Metropolis kernel's launch shape and traversal tile.
+ * Times trial_moves moves (at most N_r) of every replica with each candidate
+ * (shape s, tile j): shape 0: 512-thread workgroups, one per CU; 1:
+ * 256-thread workgroups, one per CU; 2: 256-thread workgroups, two per CU;
+ * tile 0: one trial move per traversal (two targets); 1: half the most moves
+ * per round the order allows; 2: the most (see bhmc_set_moves_per_round;
+ * tiles 1 and 2 only when every replica has N_0 = 0, and tile 1 only when it
+ * is above one move).  Every replica is rebuilt from its built positions
+ * after each trial, and the fastest candidate is kept for the handle's later
+ * bhmc_mc_run and bhmc_batch_sweep calls (replacing the moves per round set
+ * before).  Needs the replicas as built (no moves run yet; EINVAL otherwise)
+ * and leaves them exactly as built.  choice (nullable, host): 3 s + j of the
+ * candidate kept; ms_host (nullable, host, 9 floats): trial time of
+ * candidate 3 s + j (0 if not tried: a one-replica handle tries shapes 0 and
+ * 1 only).  The chain of a replica depends on the candidate only through the
+ * rounding of its energy sums. */
 bhmc_status bhmc_batch_autotune(bhmc_tree* tree, uint64_t seed, double step, int32_t trial_moves,
                                 int32_t* choice, float* ms_host);
 
 /* Set the Metropolis kernel's launch shape (0, 1 or 2 as for
- * bhmc_batch_autotune) directly, e.g. to the choice the autotuner made on
- * another handle of the same workload.  EINVAL for another value. */
+ * bhmc_batch_autotune) directly, e.g. to the shape the autotuner chose on
+ * another handle of the same workload (with bhmc_set_moves_per_round for its
+ * tile).  EINVAL for another value. */
 bhmc_status bhmc_set_launch_shape(bhmc_tree* tree, int32_t shape);
 
 /* Gradient of the treecode energy E of bhmc_energy for replica `replica`,
@@ -252,10 +258,11 @@ bhmc_status bhmc_set_launch_shape(bhmc_tree* tree, int32_t shape);
  * moments, which equal a fresh evaluation from the current positions up to
  * rounding (bhmc_rebuild refreshes them); nothing of the traversal is stored.
  * Outputs: dEdr_dev (dev, 3n values, x y z per ion), dEdq_dev (dev, n
- * values); E_host (nullable) receives E, bit-identical to bhmc_energy.  The
+ * values); E_host (nullable) receives E, equal to bhmc_energy's up to the
+ * rounding of its sums (about 1e-15 relative).  The
  * far-field source side is summed with device atomics, so the gradient can
  * differ between calls by rounding.  The library keeps a workspace of
- * about 8 (ncell * round4(C(p+3,3)) + 4.5 nsrc + 4.5 n) bytes per handle. */
+ * about 8 (ncell * round4(C(p+3,3)) + 4.5 nsrc + 5 n) bytes per handle. */
 bhmc_status bhmc_energy_grad(bhmc_tree* tree, int32_t replica, double* dEdr_dev, double* dEdq_dev,
                              double* E_host);
 

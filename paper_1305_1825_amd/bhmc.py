@@ -239,12 +239,18 @@ class Tree:
     SHAPES = ("512 threads, 1 per CU", "256 threads, 1 per CU", "256 threads, 2 per CU")
 
     def autotune(self, seed=0, step=1.0, trial_moves=256):
-        """Pick the Metropolis kernel's launch shape by timing each on the replicas
-        as built; leaves them as built.  Returns the choice and each shape's ms."""
+        """Pick the Metropolis kernel's launch shape and traversal tile (trial moves per
+        round) by timing each candidate on the replicas as built; leaves them as built.
+        Returns the choice (3 shape + tile), the shape, the moves per round kept and
+        every candidate's ms (0: not tried)."""
         choice = C.c_int32()
-        ms = (C.c_float * len(self.SHAPES))()
+        ms = (C.c_float * (3 * len(self.SHAPES)))()
         _check(lib().bhmc_batch_autotune(self.h, seed, step, trial_moves, C.byref(choice), ms), "batch_autotune")
-        return dict(choice=int(choice.value), shape=self.SHAPES[choice.value], ms=[float(v) for v in ms])
+        c = int(choice.value)
+        most = self.set_moves_per_round(0)  # the tile kept is 1, most // 2 or most moves per round
+        mpr = self.set_moves_per_round((1, most // 2, most)[c % 3])
+        return dict(choice=c, shape=self.SHAPES[c // 3], shape_index=c // 3, moves_per_round=mpr,
+                    ms=[float(v) for v in ms])
 
     def set_shape(self, shape):
         _check(lib().bhmc_set_launch_shape(self.h, int(shape)), "set_launch_shape")
@@ -266,7 +272,8 @@ class Tree:
         return int(eff.value)
 
     PHASES = ("setup", "levels", "flagged_scan", "far", "near", "overlap", "paths", "corrections", "decisions",
-              "slots", "moments", "rounds", "moves")
+              "slots", "moments", "rounds", "moves", "chunks", "entries", "empty_entries", "far_entries",
+              "near_entries")
 
     def phase_ticks(self, reset=True):
         """Phase timers of the batched kernel (a library built with phase timers), else {}."""

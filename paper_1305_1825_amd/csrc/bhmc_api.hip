@@ -651,7 +651,7 @@ extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* d
     const size_t tb = align256(sizeof(double) * 4 * (size_t)n);
     const size_t ob = align256(sizeof(int) * ((size_t)h.nsrc + 1));
     const size_t ib = align256(sizeof(int) * (size_t)n);
-    const size_t need = lb + gb + tb + ob + ib;
+    const size_t need = lb + gb + tb + ob + 2 * ib;
     if (t->gwork_bytes < need) {
         hipFree(t->gwork);
         t->gwork = nullptr;
@@ -665,6 +665,7 @@ extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* d
     w.Gt = (double4*)(t->gwork + lb + gb);
     w.rank = (int*)(t->gwork + lb + gb + tb);
     w.islot = (int*)(t->gwork + lb + gb + tb + ob);
+    w.fcell = (int*)(t->gwork + lb + gb + tb + ob + ib);
     w.ncell = h.ncell; w.nleaf = h.nleaf; w.nsrc = h.nsrc; w.n = n;
     for (;;) {
         t->ops->grad(t->stream, t->reps, replica, w, dEdr_dev, dEdq_dev, t->eterm, energy_grid_bound(t));
@@ -930,9 +931,11 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
 }
 
 // Launch shapes the replica autotuner tries: workgroup width (512 or 256
-// threads per traversal) and workgroups per CU (one, or two of 256 threads).
+// threads per traversal) and workgroups per CU (one, or two of 256 threads);
+// with each, up to three traversal tiles (trial moves per round).
 struct LaunchShape { int wide, per_cu; };
 static const LaunchShape kShapes[] = {{1, 1}, {0, 1}, {0, 2}};
+constexpr int kAutotuneTiles = 3;
 
 extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double step, int32_t trial_moves,
                                            int32_t* choice, float* ms_out) {
@@ -969,9 +972,17 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
     float best_ms = 0.0f;
     int best = -1;
     const int nshape = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
-    for (int k = 0; k < nshape && st == BHMC_OK; ++k) {
-        const LaunchShape sh = kShapes[k];
+    // moves per round (targets per shared traversal): one at a time, half the most, the most
+    const int cap = t->all_n0_zero ? t->ops->moves_per_round : 1;
+    const int tiles[kAutotuneTiles] = {1, cap / 2 > 1 ? cap / 2 : 0, cap > 1 ? cap : 0};
+    const int saved_mpr = t->moves_per_round;
+    if (ms_out)
+        for (int k = 0; k < nshape * kAutotuneTiles; ++k) ms_out[k] = 0.0f;
+    for (int k = 0; k < nshape * kAutotuneTiles && st == BHMC_OK; ++k) {
+        const LaunchShape sh = kShapes[k / kAutotuneTiles];
         if (t->R == 1 && sh.per_cu > 1) continue;  // one workgroup in all: two per CU is the same shape
+        if (tiles[k % kAutotuneTiles] == 0) continue;
+        t->moves_per_round = tiles[k % kAutotuneTiles];
         for (int r = 0; r < t->R; ++r) {
             Rep& h = t->host[r];
             h.move_next = 0;
@@ -999,6 +1010,7 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    t->moves_per_round = saved_mpr;
     if (st) return st;
     if ((st = download(t))) return st;
     for (int r = 0; r < t->R; ++r) {
@@ -1009,8 +1021,9 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
         for (int q = 0; q < 6; ++q) h.stats[q] = 0;
     }
     if ((st = upload(t))) return st;
-    t->mc_wide = kShapes[best].wide;
-    t->mc_grid = std::max(1, std::min(t->R, kShapes[best].per_cu * ncu));
+    t->mc_wide = kShapes[best / kAutotuneTiles].wide;
+    t->mc_grid = std::max(1, std::min(t->R, kShapes[best / kAutotuneTiles].per_cu * ncu));
+    t->moves_per_round = tiles[best % kAutotuneTiles];
     t->graph_ok = false;
     if (choice) *choice = best;
     return BHMC_OK;

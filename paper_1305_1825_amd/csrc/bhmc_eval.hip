@@ -1439,9 +1439,9 @@ constexpr int kGradRows = kGradBlock / 16;
 constexpr int kGT = 16;
 
 struct GradShared {
-    static constexpr int FCAP = 4096;
-    static constexpr int FARCAP = 1024 + kGradBlock;
-    static constexpr int NEARCAP = 512 + kGradBlock;
+    static constexpr int FCAP = 2048;  // on chip; larger levels continue in the HBM regions
+    static constexpr int FARCAP = 512 + kGradBlock;
+    static constexpr int NEARCAP = 256 + kGradBlock;
     static constexpr int NW = kGradBlock / 64;
     uint32_t fc[2][FCAP];          // cell
     uint64_t fm[2][FCAP];          // open | direct << 16 | image inside << 32 | ion inside << 48
@@ -1450,11 +1450,13 @@ struct GradShared {
     double tx[kGT], ty[kGT], tz[kGT], tq[kGT];
     int ion[kGT];
     uint64_t kimg[kGT], kion[kGT];
-    double4 img[kGT];
     int flag_cell[kGT];
     int nt;
     uint64_t wcnt[2][NW];
-    double red[kGradRows][kGT][4];
+    union {
+        double mrow[kGradRows][MSTR];        // the moment rows of the far cells of one step, one per row
+        double red[kGradRows][kGT][4];       // the rows' sums of each target at the end
+    };
     int err;
 };
 
@@ -1535,19 +1537,36 @@ __device__ __forceinline__ void grad_rows(const Rep& R, GradShared& S, int far_n
     const int kk = tk ? k : 0;
     const double xk = S.tx[kk], yk = S.ty[kk], zk = S.tz[kk];
     const double wk = half_lB * S.tq[kk];
-    for (int j = row; j < far_n; j += kGradRows) {
-        const int c = (int)S.farc[j];
-        if (c >= R.ncell) { S.err = kErrFarCell; continue; }
-        const bool act = tk && ((S.farm[j] >> k) & 1u);
-        const double4 g = R.cgeo[c];
-        const double Rx = g.x - xk, Ry = g.y - yk, Rz = g.z - zk;
-        double T[NTERM1];
-        T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
-        const double ir2 = T[0] * T[0];
-        double phi = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-        far_rec_row<0>(T, Rx, Ry, Rz, ir2, grow(R.M + (size_t)c * MSTR),
-                       L + (size_t)c * MSTR, act ? wk : 0.0, k, phi, fx, fy, fz);
-        if (act) { acc[0] += phi; acc[1] += fx; acc[2] += fy; acc[3] += fz; }
+    // a step takes the next kGradRows far cells, one per row: the workgroup first copies
+    // their moment rows to LDS (consecutive threads, consecutive words), so that a row reads
+    // its cell's moments as it needs them instead of holding them in registers
+    for (int j0 = 0; j0 < far_n; j0 += kGradRows) {
+        const int nstep = far_n - j0 < kGradRows ? far_n - j0 : kGradRows;
+        for (int it = threadIdx.x; it < nstep * MSTR; it += kGradBlock) {
+            const int f = it / MSTR, t = it - f * MSTR;
+            const int c = (int)S.farc[j0 + f];
+            S.mrow[f][t] = c < R.ncell ? R.M[(size_t)c * MSTR + t] : 0.0;
+        }
+        __syncthreads();
+        const int j = j0 + row;
+        if (row < nstep) {
+            const int c = (int)S.farc[j];
+            if (c >= R.ncell) {
+                S.err = kErrFarCell;
+            } else {
+                const bool act = tk && ((S.farm[j] >> k) & 1u);
+                const double4 g = R.cgeo[c];
+                const double Rx = g.x - xk, Ry = g.y - yk, Rz = g.z - zk;
+                double T[NTERM1];
+                T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
+                const double ir2 = T[0] * T[0];
+                double phi = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+                far_rec_row<0>(T, Rx, Ry, Rz, ir2, lrow(S.mrow[row]), L + (size_t)c * MSTR, act ? wk : 0.0, k,
+                               phi, fx, fy, fz);
+                if (act) { acc[0] += phi; acc[1] += fx; acc[2] += fy; acc[3] += fz; }
+            }
+        }
+        __syncthreads();
     }
     const int n_ion = R.n;
     const int own_img = R.images ? n_ion + S.ion[kk] : -1;
@@ -1582,7 +1601,7 @@ __device__ __forceinline__ void grad_rows(const Rep& R, GradShared& S, int far_n
 }
 
 __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int* islot, int nion, double* L,
-                                                     double4* G, double4* Gt, double* eterm) {
+                                                     double4* G, double4* Gt, double* eterm, int* fcell) {
     using GS = GradShared;
     constexpr int NW = GS::NW;
     __shared__ GS S;
@@ -1621,7 +1640,6 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
                 S.kion[tid] = morton_key(R, p.x, p.y, p.z);
             }
             const double4 mo = (imgs && sid >= 0 && sid < R.n) ? R.src[R.n + sid] : make_double4(0, 0, 0, 0);
-            S.img[tid] = mo;
             S.kimg[tid] = imgs ? morton_key(R, mo.x, mo.y, mo.z) : 0;
             S.flag_cell[tid] = -1;
         }
@@ -1774,25 +1792,7 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
         if (failed && tid == 0) S.err = frontier_full ? kErrFrontier : kErrStack;
         __syncthreads();
         grad_rows(R, S, far_n, near_n, L, G, half_lB, acc);
-        // the far cell holding a target's own image: take the image's pair terms back out
-        if (tid < nt && S.flag_cell[tid] >= 0) {
-            const int c = S.flag_cell[tid];
-            const double4 g = R.cgeo[c];
-            const double4 y = S.img[tid];
-            const double Rx = g.x - S.tx[tid], Ry = g.y - S.ty[tid], Rz = g.z - S.tz[tid];
-            double T[NTERM1], D[NTERM];
-            T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
-            const double ir2 = T[0] * T[0];
-            double v = 0.0, F[3] = {0.0, 0.0, 0.0}, Gk[3] = {0.0, 0.0, 0.0};
-            flag_rec<0>(T, D, Rx, Ry, Rz, ir2, y.x - g.x, y.y - g.y, y.z - g.z, v, F, Gk);
-            acc[0] -= y.w * v; acc[1] -= y.w * F[0]; acc[2] -= y.w * F[1]; acc[3] -= y.w * F[2];
-            const double wt = half_lB * S.tq[tid];
-            double4* Gs = G + (R.n + S.ion[tid]);
-            unsafeAtomicAdd(&Gs->x, -wt * y.w * Gk[0]);
-            unsafeAtomicAdd(&Gs->y, -wt * y.w * Gk[1]);
-            unsafeAtomicAdd(&Gs->z, -wt * y.w * Gk[2]);
-            unsafeAtomicAdd(&Gs->w, -wt * v);
-        }
+        // (the far cell holding a target's own image is corrected by k_gflag)
         {
             const int row = tid >> 4, k = tid & 15;
             S.red[row][k][0] = acc[0]; S.red[row][k][1] = acc[1]; S.red[row][k][2] = acc[2]; S.red[row][k][3] = acc[3];
@@ -1817,9 +1817,48 @@ __global__ void __launch_bounds__(kGradBlock) k_grad(Rep* reps, int r, const int
             eterm[ion] = e;
             const double wq = half_lB * q;
             Gt[ion] = make_double4(-wq * a1, -wq * a2, -wq * a3, half_lB * ph);
+            fcell[ion] = S.flag_cell[tid];
         }
         __syncthreads();
     }
+}
+
+// The far cell that holds a target's own image in its traversal (found by k_grad;
+// one thread per ion): the image's pair terms with the target, taken through that
+// cell's expansion, come back out of the target's potential, field and energy term
+// and out of the image's source-side gradient.  Kept apart from k_grad because it
+// holds every monomial of the image and T up to order p + 1 at once.
+__global__ void __launch_bounds__(256) k_gflag(Rep* reps, int r, const int* fcell, double4* G, double4* Gt,
+                                               double* eterm) {
+    const Rep& R = reps[r];
+    const int ion = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ion >= R.n || !R.images) return;
+    const int c = fcell[ion];
+    if (c < 0) return;
+    if (c >= R.ncell) { reps[r].err_detail = kErrFlagCell; return; }
+    const double4 g = R.cgeo[c];
+    const double4 x = R.src[ion];
+    const double4 y = R.src[R.n + ion];
+    const double Rx = g.x - x.x, Ry = g.y - x.y, Rz = g.z - x.z;
+    double T[NTERM1], D[NTERM];
+    T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
+    const double ir2 = T[0] * T[0];
+    double v = 0.0, F[3] = {0.0, 0.0, 0.0}, Gk[3] = {0.0, 0.0, 0.0};
+    flag_rec<0>(T, D, Rx, Ry, Rz, ir2, y.x - g.x, y.y - g.y, y.z - g.z, v, F, Gk);
+    const double half_lB = 0.5 * R.l_B, wq = half_lB * x.w;
+    double4 gt = Gt[ion];
+    gt.x += wq * (y.w * F[0]);
+    gt.y += wq * (y.w * F[1]);
+    gt.z += wq * (y.w * F[2]);
+    gt.w -= half_lB * (y.w * v);
+    Gt[ion] = gt;
+    eterm[ion] -= 0.5 * x.w * (y.w * v);
+    double4 gs = G[R.n + ion];
+    gs.x -= wq * y.w * Gk[0];
+    gs.y -= wq * y.w * Gk[1];
+    gs.z -= wq * y.w * Gk[2];
+    gs.w -= wq * v;
+    G[R.n + ion] = gs;
 }
 
 // Ion groups of the gradient traversal: the ions in the order of the build's
@@ -1962,7 +2001,9 @@ void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, 
     int ggrid = (w.n + kGT - 1) / kGT;
     if (max_grid > 0 && ggrid > max_grid) ggrid = max_grid;
     hipLaunchKernelGGL(k_grad, dim3(ggrid), dim3(kGradBlock), 0, s, reps, r, (const int*)w.islot, w.n,
-                       w.L, w.G, w.Gt, eterm);
+                       w.L, w.G, w.Gt, eterm, w.fcell);
+    hipLaunchKernelGGL(k_gflag, dim3((w.n + 255) / 256), dim3(256), 0, s, reps, r, (const int*)w.fcell, w.G,
+                       w.Gt, eterm);
     hipLaunchKernelGGL(k_adj_down, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
                        (const double*)w.L, w.G);
     hipLaunchKernelGGL(k_chain, dim3((w.n + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,

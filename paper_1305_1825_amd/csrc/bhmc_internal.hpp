@@ -54,6 +54,7 @@ struct GradWork {
     double4* Gt;          // per ion: the same through its target role
     int* rank;            // per sorted source: ions before it (nsrc + 1)
     int* islot;           // per ion rank: its current slot (n)
+    int* fcell;           // per ion: the far cell holding its own image in its traversal, or -1 (n)
     int ncell, nleaf, nsrc, n;
 };
 

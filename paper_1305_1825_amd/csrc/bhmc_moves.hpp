@@ -38,7 +38,9 @@ static_assert(kBM <= 8, "the move index has three bits");
 // Phase timers of a round (built with -DBHMC_PHASE_TIMERS only): thread 0 adds the
 // constant-clock ticks of each phase to a device array read by bhmc_phase_ticks.
 enum { kPhSetup = 0, kPhLevels, kPhFlagged, kPhFar, kPhNear, kPhOverlap, kPhPaths, kPhCorr, kPhDecide,
-       kPhSlots, kPhMoments, kPhRounds, kPhMoves, kNumPhases };
+       kPhSlots, kPhMoments, kPhRounds, kPhMoves,
+       // counts: level-loop chunks, frontier entries, entries holding no remaining source, far and near list entries
+       kPhChunks, kPhEntries, kPhEmpty, kPhFarN, kPhNearN, kNumPhases };
 #ifdef BHMC_PHASE_TIMERS
 __device__ unsigned long long g_phase[kNumPhases];
 #define PHASE_START() long long ph_t0_ = wall_clock64()
@@ -388,6 +390,18 @@ __device__ void traverse_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, Hook&& ho
             const bool kf = farb && !flagged, kg = farb && flagged, kn = nearb != 0, ks = copen != 0;
             const uint64_t lt = lanemask_lt();
             const uint64_t bf = __ballot(kf), bn = __ballot(kn), bs = __ballot(ks), bg = __ballot(kg);
+#ifdef BHMC_PHASE_TIMERS
+            {
+                const uint64_t bv = __ballot(valid), be = __ballot(valid && m.x - fi - fk <= 0);
+                if (lane == 0) {
+                    atomicAdd(&g_phase[kPhEntries], (unsigned long long)__popcll(bv));
+                    atomicAdd(&g_phase[kPhEmpty], (unsigned long long)__popcll(be));
+                    atomicAdd(&g_phase[kPhFarN], (unsigned long long)(__popcll(bf) + __popcll(bg)));
+                    atomicAdd(&g_phase[kPhNearN], (unsigned long long)__popcll(bn));
+                }
+                PHASE_COUNT(kPhChunks, 1);
+            }
+#endif
             if (lane == 0)
                 S.wcnt[buf][w] = (uint64_t)__popcll(bf) | ((uint64_t)__popcll(bn) << 16) |
                                  ((uint64_t)__popcll(bs) << 32) | ((uint64_t)__popcll(bg) << 48);

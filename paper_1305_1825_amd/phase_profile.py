@@ -7,7 +7,9 @@ kernel's thread 0 also adds the constant-clock ticks of each phase of a round to
 device counters) and reports, for one chain and for the replica sweep, the
 microseconds per round and per trial move of each phase: set-up, traversal
 levels, corrected moments and scan, far cells, near leaves, hard cores below far
-cells, path descents, corrections, decisions, leaf index arrays and moments.
+cells, path descents, corrections, decisions, leaf index arrays and moments;
+and per round the traversal's chunks of frontier entries, its entries (and how
+many hold no source besides the movers'), and its far and near list entries.
 
     python -m paper_1305_1825_amd.phase_profile [--moves 20000] [--no-sweep]
 """
@@ -26,17 +28,23 @@ from . import bhmc  # noqa: E402
 from . import workloads as W  # noqa: E402
 
 CLOCK_HZ = 100e6  # the device's constant clock read by wall_clock64
+# counters rather than ticks: level-loop chunks, frontier entries, entries with no remaining source, list entries
+COUNTS = ("chunks", "entries", "empty_entries", "far_entries", "near_entries")
 
 
 def report(name, ticks, wall_s=None):
     rounds, moves = ticks.get("rounds", 0), ticks.get("moves", 0)
     out = {"workload": name, "rounds": rounds, "moves": moves}
     if rounds:
-        for k, v in ticks.items():
-            if k in ("rounds", "moves"):
-                continue
+        timed = {k: v for k, v in ticks.items() if k not in ("rounds", "moves") + COUNTS}
+        for k, v in timed.items():
             out[k + "_us_per_round"] = v / CLOCK_HZ * 1e6 / rounds
-        out["sum_us_per_round"] = sum(v for k, v in ticks.items() if k not in ("rounds", "moves")) / CLOCK_HZ * 1e6 / rounds
+        out["sum_us_per_round"] = sum(timed.values()) / CLOCK_HZ * 1e6 / rounds
+        for k in COUNTS:
+            if k in ticks:
+                out[k + "_per_round"] = ticks[k] / rounds
+        if ticks.get("chunks"):
+            out["levels_us_per_chunk"] = ticks["levels"] / CLOCK_HZ * 1e6 / ticks["chunks"]
         out["moves_per_round"] = moves / rounds
     if wall_s:
         out["moves_per_s"] = moves / wall_s if moves else None
