@@ -32,6 +32,7 @@ constexpr int kMvSh = 24;
 constexpr int kOpSh = 27;
 constexpr uint32_t kMbIon = 1u << 29, kMbImg = 1u << 30;
 constexpr int kPathCells = kBM * 4 * kMaxLevels;
+constexpr int kChunk = 2;  // frontier entries per lane per chunk of the traversal's level loop
 
 static_assert(kBM <= 8, "the move index has three bits");
 
@@ -62,8 +63,8 @@ __device__ unsigned long long g_phase[kNumPhases];
 template <int BLOCK>
 struct BTrav {
     static constexpr int FCAP = 4096;
-    static constexpr int FARCAP = 2048 + BLOCK;
-    static constexpr int NEARCAP = 1024 + BLOCK;
+    static constexpr int FARCAP = 2048 + kChunk * BLOCK;
+    static constexpr int NEARCAP = 1024 + kChunk * BLOCK;
     static constexpr int OVLCAP = 512;
     static constexpr int NW = BLOCK / 64;
     // the traversal's lists, free once it has ended: then per-axis power tables of the commit
@@ -83,7 +84,7 @@ struct BTrav {
     double Mx[4 * kBM][MSTR];
     uint32_t ovl[OVLCAP];
     int n_ovl, near_tot, err;
-    uint64_t wcnt[2][NW];
+    uint64_t wcnt[2][kChunk][NW];
     double red[NW][kBT];
     uint32_t mi[NTERM];
     int cnt2[2];
@@ -336,86 +337,113 @@ __device__ void traverse_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, Hook&& ho
     PHASE_START();
     for (int level = MV.level0; fs > 0 && !failed; ++level) {
         int next_n = 0;
-        for (int base = 0; base < fs; base += BLOCK) {
-            if (far_n > TS::FARCAP - BLOCK) {
+        // a chunk is kChunk entries per lane: every lane issues the cell loads of all its
+        // entries before classifying any, so their latencies overlap and a wide level takes
+        // fewer barriers; outputs keep the order of the entries
+        for (int base = 0; base < fs; base += kChunk * BLOCK) {
+            if (far_n > TS::FARCAP - kChunk * BLOCK) {
                 __syncthreads();
                 far_pass_mb<BLOCK>(R, S, MV, far_n, 0, acc);
                 far_n = 0;
                 __syncthreads();
             }
-            if (near_n > TS::NEARCAP - BLOCK) {
+            if (near_n > TS::NEARCAP - kChunk * BLOCK) {
                 __syncthreads();
                 const int total = near_scan_mb<BLOCK>(S, near_n);
                 near_pass_mb<BLOCK>(R, S, MV, near_n, total, acc);
                 near_n = 0;
                 __syncthreads();
             }
-            const int j = base + tid;
-            const bool valid = j < fs;
-            const uint32_t e = valid ? (rg ? gfr[(size_t)cur * gcap + j] : S.front[cur][j]) : 0u;
-            const int c = (int)(e & kCellMask), b = mv_of(e);
-            const int fi = (e & kMbIon) ? 1 : 0, fk = (e & kMbImg) ? 1 : 0;
-            const uint32_t open = (e >> kOpSh) & 3u;
-            int4 m = make_int4(0, -1, 0, 0);
-            double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (valid && c < R.ncell) { m = gload(R.cm + c); g = gload(R.cgeo + c); }
+            uint32_t e[kChunk];
+            int4 m[kChunk];
+            double4 g[kChunk];
+            bool valid[kChunk];
+#pragma unroll
+            for (int h = 0; h < kChunk; ++h) {
+                const int j = base + h * BLOCK + tid;
+                valid[h] = j < fs;
+                e[h] = valid[h] ? (rg ? gfr[(size_t)cur * gcap + j] : S.front[cur][j]) : 0u;
+                m[h] = make_int4(0, -1, 0, 0);
+                g[h] = make_double4(0.0, 0.0, 0.0, 0.0);
+                const int c = (int)(e[h] & kCellMask);
+                if (valid[h] && c < R.ncell) { m[h] = gload(R.cm + c); g[h] = gload(R.cgeo + c); }
+            }
             if (base == 0) hook(level);
-            uint32_t farb = 0, nearb = 0, copen = 0;
-            if (valid && c >= R.ncell) {
-                S.err = kErrFrontCell;
-            } else if (valid) {
-                const int np = m.x - fi - fk;
-                if (m.y >= 0 && m.y + 8 > R.ncell) {
-                    S.err = kErrChildLink;
-                } else if (np > 0) {
-                    const int t0 = 2 * b;
-                    const double dx0 = g.x - MV.tx[t0], dy0 = g.y - MV.ty[t0], dz0 = g.z - MV.tz[t0];
-                    const double dx1 = g.x - MV.tx[t0 + 1], dy1 = g.y - MV.ty[t0 + 1], dz1 = g.z - MV.tz[t0 + 1];
-                    const double d20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
-                    const double d21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
-                    const double h2 = 3.0 * (g.w * g.w);
-                    const uint32_t mac = (h2 <= R.theta2 * d20 ? 1u : 0u) | (h2 <= R.theta2 * d21 ? 2u : 0u);
-                    const bool internal = m.y >= 0;
-                    farb = open & mac;
-                    const uint32_t rest = open & ~farb;
-                    copen = internal ? rest : 0u;
-                    nearb = internal ? 0u : rest;
-                    if ((farb & 2u) && box_dist2(g, MV.tx[t0 + 1], MV.ty[t0 + 1], MV.tz[t0 + 1]) <= R.reach2) {
-                        const int slot = atomicAdd(&S.n_ovl, 1);
-                        if (slot < TS::OVLCAP) S.ovl[slot] = (uint32_t)c | ((uint32_t)b << kMvSh); else S.err = kErrStack;
+            uint32_t farb[kChunk], nearb[kChunk], copen[kChunk];
+            uint64_t bf[kChunk], bn[kChunk], bs[kChunk], bg[kChunk];
+            const uint64_t lt = lanemask_lt();
+#pragma unroll
+            for (int h = 0; h < kChunk; ++h) {
+                const int c = (int)(e[h] & kCellMask), b = mv_of(e[h]);
+                const int fi = (e[h] & kMbIon) ? 1 : 0, fk = (e[h] & kMbImg) ? 1 : 0;
+                const uint32_t open = (e[h] >> kOpSh) & 3u;
+                farb[h] = 0; nearb[h] = 0; copen[h] = 0;
+                if (valid[h] && c >= R.ncell) {
+                    S.err = kErrFrontCell;
+                } else if (valid[h]) {
+                    const int np = m[h].x - fi - fk;
+                    if (m[h].y >= 0 && m[h].y + 8 > R.ncell) {
+                        S.err = kErrChildLink;
+                    } else if (np > 0) {
+                        const int t0 = 2 * b;
+                        const double4 gg = g[h];
+                        const double dx0 = gg.x - MV.tx[t0], dy0 = gg.y - MV.ty[t0], dz0 = gg.z - MV.tz[t0];
+                        const double dx1 = gg.x - MV.tx[t0 + 1], dy1 = gg.y - MV.ty[t0 + 1], dz1 = gg.z - MV.tz[t0 + 1];
+                        const double d20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
+                        const double d21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
+                        const double h2 = 3.0 * (gg.w * gg.w);
+                        const uint32_t mac = (h2 <= R.theta2 * d20 ? 1u : 0u) | (h2 <= R.theta2 * d21 ? 2u : 0u);
+                        const bool internal = m[h].y >= 0;
+                        farb[h] = open & mac;
+                        const uint32_t rest = open & ~farb[h];
+                        copen[h] = internal ? rest : 0u;
+                        nearb[h] = internal ? 0u : rest;
+                        if ((farb[h] & 2u) && box_dist2(gg, MV.tx[t0 + 1], MV.ty[t0 + 1], MV.tz[t0 + 1]) <= R.reach2) {
+                            const int slot = atomicAdd(&S.n_ovl, 1);
+                            if (slot < TS::OVLCAP) S.ovl[slot] = (uint32_t)c | ((uint32_t)b << kMvSh); else S.err = kErrStack;
+                        }
                     }
                 }
-            }
-            const bool flagged = (fi | fk) != 0;
-            const bool kf = farb && !flagged, kg = farb && flagged, kn = nearb != 0, ks = copen != 0;
-            const uint64_t lt = lanemask_lt();
-            const uint64_t bf = __ballot(kf), bn = __ballot(kn), bs = __ballot(ks), bg = __ballot(kg);
+                const bool flagged = (fi | fk) != 0;
+                bf[h] = __ballot(farb[h] && !flagged);
+                bg[h] = __ballot(farb[h] && flagged);
+                bn[h] = __ballot(nearb[h] != 0);
+                bs[h] = __ballot(copen[h] != 0);
 #ifdef BHMC_PHASE_TIMERS
-            {
-                const uint64_t bv = __ballot(valid), be = __ballot(valid && m.x - fi - fk <= 0);
-                if (lane == 0) {
-                    atomicAdd(&g_phase[kPhEntries], (unsigned long long)__popcll(bv));
-                    atomicAdd(&g_phase[kPhEmpty], (unsigned long long)__popcll(be));
-                    atomicAdd(&g_phase[kPhFarN], (unsigned long long)(__popcll(bf) + __popcll(bg)));
-                    atomicAdd(&g_phase[kPhNearN], (unsigned long long)__popcll(bn));
+                {
+                    const uint64_t bv = __ballot(valid[h]), be = __ballot(valid[h] && m[h].x - fi - fk <= 0);
+                    if (lane == 0) {
+                        atomicAdd(&g_phase[kPhEntries], (unsigned long long)__popcll(bv));
+                        atomicAdd(&g_phase[kPhEmpty], (unsigned long long)__popcll(be));
+                        atomicAdd(&g_phase[kPhFarN], (unsigned long long)(__popcll(bf[h]) + __popcll(bg[h])));
+                        atomicAdd(&g_phase[kPhNearN], (unsigned long long)__popcll(bn[h]));
+                    }
                 }
-                PHASE_COUNT(kPhChunks, 1);
-            }
 #endif
-            if (lane == 0)
-                S.wcnt[buf][w] = (uint64_t)__popcll(bf) | ((uint64_t)__popcll(bn) << 16) |
-                                 ((uint64_t)__popcll(bs) << 32) | ((uint64_t)__popcll(bg) << 48);
+                if (lane == 0)
+                    S.wcnt[buf][h][w] = (uint64_t)__popcll(bf[h]) | ((uint64_t)__popcll(bn[h]) << 16) |
+                                        ((uint64_t)__popcll(bs[h]) << 32) | ((uint64_t)__popcll(bg[h]) << 48);
+            }
+            PHASE_COUNT(kPhChunks, 1);
             __syncthreads();
-            uint64_t before = 0, tot = 0;
+            // offsets: the entries of part h of every wave come after all of part h - 1
+            uint64_t before[kChunk], tot[kChunk];
 #pragma unroll
-            for (int ww = 0; ww < NW; ++ww) {
-                const uint64_t v = S.wcnt[buf][ww];
-                before += ww < w ? v : 0ull;
-                tot += v;
+            for (int h = 0; h < kChunk; ++h) {
+                before[h] = 0; tot[h] = 0;
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) {
+                    const uint64_t v = S.wcnt[buf][h][ww];
+                    before[h] += ww < w ? v : 0ull;
+                    tot[h] += v;
+                }
             }
             buf ^= 1;
-            const int tf = (int)(tot & 0xffff), tn = (int)((tot >> 16) & 0xffff);
-            const int ts = (int)((tot >> 32) & 0xffff), tg = (int)(tot >> 48);
+            uint64_t all = 0;
+#pragma unroll
+            for (int h = 0; h < kChunk; ++h) all += tot[h];
+            const int tf = (int)(all & 0xffff), tn = (int)((all >> 16) & 0xffff);
+            const int ts = (int)((all >> 32) & 0xffff), tg = (int)(all >> 48);
             if (nflag + tg > 4 * kBM) {  // uniform
                 failed = true;
                 break;
@@ -428,28 +456,39 @@ __device__ void traverse_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, Hook&& ho
                 for (int k = tid; k < next_n; k += BLOCK) gfr[(size_t)(cur ^ 1) * gcap + k] = S.front[cur ^ 1][k];
                 wg = true;
             }
-            const uint32_t flags = e & (kMbIon | kMbImg);
-            const uint32_t mvb = (uint32_t)b << kMvSh;
-            if (kf) S.farl[far_n + (int)(before & 0xffff) + __popcll(bf & lt)] = (uint32_t)c | mvb | (farb << kOpSh);
-            if (kg) S.flagl[nflag + (int)(before >> 48) + __popcll(bg & lt)] = (uint32_t)c | mvb | (farb << kOpSh) | flags;
-            if (kn) {
-                const int o = near_n + (int)((before >> 16) & 0xffff) + __popcll(bn & lt);
-                S.nearl[o] = (uint32_t)c | mvb | (nearb << kOpSh) | flags;
-                S.near_base[o] = m.z;
-                S.near_pre[o] = m.x;
-                if (m.x < 0 || m.z < 0 || m.z + m.x > R.pool) { S.near_pre[o] = 0; S.err = kErrNearSlots; }
-            }
-            if (ks) {
-                const int o = next_n + 8 * ((int)((before >> 32) & 0xffff) + __popcll(bs & lt));
-                const int dig_i = fi ? key_digit(MV.key[b][0], level + 1) : -1;
-                const int dig_k = fk ? key_digit(MV.key[b][2], level + 1) : -1;
-                const uint32_t hdr = mvb | (copen << kOpSh);
+            uint64_t prior = 0;  // the parts before h, summed over the whole workgroup
 #pragma unroll
-                for (int d = 0; d < 8; ++d) {
-                    const uint32_t fl = (d == dig_i ? kMbIon : 0u) | (d == dig_k ? kMbImg : 0u);
-                    const uint32_t ne = (uint32_t)(m.y + d) | hdr | fl;
-                    if (wg) gfr[(size_t)(cur ^ 1) * gcap + o + d] = ne;
-                    else S.front[cur ^ 1][o + d] = ne;
+            for (int h = 0; h < kChunk; ++h) {
+                const uint64_t at = prior + before[h];
+                prior += tot[h];
+                const int c = (int)(e[h] & kCellMask), b = mv_of(e[h]);
+                const int fi = (e[h] & kMbIon) ? 1 : 0, fk = (e[h] & kMbImg) ? 1 : 0;
+                const bool flagged = (fi | fk) != 0;
+                const uint32_t flags = e[h] & (kMbIon | kMbImg);
+                const uint32_t mvb = (uint32_t)b << kMvSh;
+                if (farb[h] && !flagged)
+                    S.farl[far_n + (int)(at & 0xffff) + __popcll(bf[h] & lt)] = (uint32_t)c | mvb | (farb[h] << kOpSh);
+                if (farb[h] && flagged)
+                    S.flagl[nflag + (int)(at >> 48) + __popcll(bg[h] & lt)] = (uint32_t)c | mvb | (farb[h] << kOpSh) | flags;
+                if (nearb[h]) {
+                    const int o = near_n + (int)((at >> 16) & 0xffff) + __popcll(bn[h] & lt);
+                    S.nearl[o] = (uint32_t)c | mvb | (nearb[h] << kOpSh) | flags;
+                    S.near_base[o] = m[h].z;
+                    S.near_pre[o] = m[h].x;
+                    if (m[h].x < 0 || m[h].z < 0 || m[h].z + m[h].x > R.pool) { S.near_pre[o] = 0; S.err = kErrNearSlots; }
+                }
+                if (copen[h]) {
+                    const int o = next_n + 8 * ((int)((at >> 32) & 0xffff) + __popcll(bs[h] & lt));
+                    const int dig_i = fi ? key_digit(MV.key[b][0], level + 1) : -1;
+                    const int dig_k = fk ? key_digit(MV.key[b][2], level + 1) : -1;
+                    const uint32_t hdr = mvb | (copen[h] << kOpSh);
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        const uint32_t fl = (d == dig_i ? kMbIon : 0u) | (d == dig_k ? kMbImg : 0u);
+                        const uint32_t ne = (uint32_t)(m[h].y + d) | hdr | fl;
+                        if (wg) gfr[(size_t)(cur ^ 1) * gcap + o + d] = ne;
+                        else S.front[cur ^ 1][o + d] = ne;
+                    }
                 }
             }
             far_n += tf; near_n += tn; nflag += tg; next_n += 8 * ts;
