@@ -786,22 +786,23 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
     }
     __syncthreads();
     PHASE(kPhCorr);
-    // ---- decisions, in move order, by the first wave.  Everything the loop reads is first
-    // brought into registers at once: lane b holds move b's own data, lane j its part of the
-    // sums of every later move; the loop then only shuffles.
+    // ---- decisions, in move order, by the first wave.  Lane b holds everything move b needs,
+    // what every earlier move of the round adds to it included, so deciding move b is lane b's
+    // own arithmetic on the mask of the moves accepted so far; one read of that lane's verdict
+    // then updates the mask for the next move.
     if (tid < 64) {
         const int lane = tid;
+        const bool mine = lane < nb;
         double cr0[kBM], cr1[kBM];
         int ei_r[kBM], em_r[kBM];
 #pragma unroll
-        for (int b = 0; b < kBM; ++b) {
-            const bool v = lane < b && b < nb;
-            cr0[b] = v ? MV.corr[lane][b][0] : 0.0;
-            cr1[b] = v ? MV.corr[lane][b][1] : 0.0;
-            ei_r[b] = v ? MV.e_ion[b][lane] : 0;
-            em_r[b] = v ? MV.e_img[b][lane] : 0;
+        for (int j = 0; j < kBM; ++j) {
+            const bool v = mine && j < lane;
+            cr0[j] = v ? MV.corr[j][lane][0] : 0.0;
+            cr1[j] = v ? MV.corr[j][lane][1] : 0.0;
+            ei_r[j] = v ? MV.e_ion[lane][j] : 0;
+            em_r[j] = v ? MV.e_img[lane][j] : 0;
         }
-        const bool mine = lane < nb;
         const int my_wall = mine ? MV.wall[lane] : 1;
         const int my_fixed = mine ? MV.ovl_fixed[lane] : 0;
         const uint32_t my_moved = mine ? MV.ovl_moved[lane] : 0u, my_new = mine ? MV.ovl_new[lane] : 0u;
@@ -823,51 +824,44 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
 #pragma unroll
         for (int b = 0; b < kBM; ++b) {
             if (b >= nb || ended) continue;  // uniform
-            int reason = 0;
+            // verdict of lane b: bit 0 accepted, bit 1 its commit would overflow a leaf index
+            // array, bit 2 its tracked leaves are not where its keys lead
+            int out = 0, reason = 0;
             double dE = kInf;
-            bool accept = false;
-            const int wall = __shfl(my_wall, b, 64);
-            const int fixed = __shfl(my_fixed, b, 64);
-            const uint32_t moved = (uint32_t)__shfl((int)my_moved, b, 64);
-            const uint32_t nw = (uint32_t)__shfl((int)my_new, b, 64);
-            if (wall) {
-                reason = 1;
-            } else if (fixed != 0 || (moved & ~acc_mask) != 0u || (nw & acc_mask) != 0u) {
-                reason = 2;
-            } else {
-                const bool on = lane < kBM && ((acc_mask >> lane) & 1u);  // only lanes j < b can be set
-                double c1 = on ? cr1[b] : 0.0, c0 = on ? cr0[b] : 0.0;
-                int ei = on ? ei_r[b] : 0, em = on ? em_r[b] : 0;
+            if (lane == b) {
+                if (my_wall) {
+                    reason = 1;
+                } else if (my_fixed != 0 || (my_moved & ~acc_mask) != 0u || (my_new & acc_mask) != 0u) {
+                    reason = 2;
+                } else {
+                    double c1 = 0.0, c0 = 0.0;
+                    int ei = 0, em = 0;
 #pragma unroll
-                for (int off = 4; off >= 1; off >>= 1) {  // the moves sit in the first 8 lanes
-                    c1 += __shfl_xor(c1, off, 64);
-                    c0 += __shfl_xor(c0, off, 64);
-                    ei += __shfl_xor(ei, off, 64);
-                    em += __shfl_xor(em, off, 64);
-                }
-                c1 = __shfl(c1, 0, 64); c0 = __shfl(c0, 0, 64);
-                ei = __shfl(ei, 0, 64); em = __shfl(em, 0, 64);
-                const double pn = __shfl(my_pn, b, 64) + c1, po = __shfl(my_po, b, 64) + c0;
-                dE = R.l_B * __shfl(my_q, b, 64) * (pn - po) + __shfl(my_d0, b, 64);
-                accept = dE <= 0.0 || __shfl(my_alpha, b, 64) <= exp(-dE);
-                if (accept) {
-                    if (!__shfl(my_sane, b, 64)) { err = kErrCommitSlot; done = b; ended = true; continue; }
-                    // would a leaf index array overflow?
-                    const int cio = __shfl(my_cio, b, 64), cin = __shfl(my_cin, b, 64);
-                    bool ok = !(cin != cio && __shfl(my_l0.x, b, 64) + ei + 1 > __shfl(my_l0.w, b, 64));
-                    if (imgs) {
-                        const int cmo = __shfl(my_cmo, b, 64), cmn = __shfl(my_cmn, b, 64);
-                        if (cmn != cmo) {
-                            int c = __shfl(my_l1.x, b, 64) + em;
-                            if (cin != cio) { if (cmn == cin) c += 1; if (cmn == cio) c -= 1; }
-                            if (c + 1 > __shfl(my_l1.w, b, 64)) ok = false;
+                    for (int j = 0; j < kBM; ++j)
+                        if (j < b && ((acc_mask >> j) & 1u)) { c1 += cr1[j]; c0 += cr0[j]; ei += ei_r[j]; em += em_r[j]; }
+                    const double pn = my_pn + c1, po = my_po + c0;
+                    dE = R.l_B * my_q * (pn - po) + my_d0;
+                    if (dE <= 0.0 || my_alpha <= exp(-dE)) {
+                        if (!my_sane) {
+                            out = 4;
+                        } else {
+                            // would a leaf index array overflow?
+                            bool ok = !(my_cin != my_cio && my_l0.x + ei + 1 > my_l0.w);
+                            if (imgs && my_cmn != my_cmo) {
+                                int c = my_l1.x + em;
+                                if (my_cin != my_cio) { if (my_cmn == my_cin) c += 1; if (my_cmn == my_cio) c -= 1; }
+                                if (c + 1 > my_l1.w) ok = false;
+                            }
+                            out = ok ? 1 : 2;
                         }
                     }
-                    if (!ok) { stop = -6; done = b; ended = true; continue; }
-                    acc_mask |= 1u << b;
                 }
             }
-            if (lane == b) { my_reason = reason; my_dE = dE; my_acc = accept ? 1 : 0; }
+            out = __builtin_amdgcn_readlane(out, b);  // uniform from here
+            if (out & 4) { err = kErrCommitSlot; done = b; ended = true; continue; }
+            if (out & 2) { stop = -6; done = b; ended = true; continue; }
+            if (out & 1) acc_mask |= 1u << b;
+            if (lane == b) { my_reason = reason; my_dE = dE; my_acc = out & 1; }
         }
         if (mine) {
             MV.reason[lane] = my_reason;
