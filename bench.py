@@ -79,11 +79,12 @@ def log(*a):
 
 
 # ---------------------------------------------------------------- algorithmic bytes
-def algorithmic_bytes_per_move(c, n_sample=400, replica=0):
+def algorithmic_bytes_per_move(c, n_sample=400, replica=0, accept=0.9):
     """Bytes a move must touch at least, from the oracle's interaction counts:
-    40 B per visited cell (centre, half side, count, link), 8 B per moment of
-    every far cell, 32 B per near source (x, y, z, q), and for an accepted move
-    a read and a write of every moment on the root paths."""
+    48 B per visited cell (centre and half side, 32 B; count, link, leaf slot
+    base and capacity, 16 B), 8 B per moment of every far cell, 32 B per near
+    source (x, y, z, q), and for an accepted move a read and a write of every
+    moment on the root paths."""
     import oracle as O
     P = c["params"]
     o = O.Tree(P, c["x"], c["y"], c["z"], c["q"])
@@ -99,12 +100,12 @@ def algorithmic_bytes_per_move(c, n_sample=400, replica=0):
         if reason == 0:
             tot_v += cnt[0]; tot_f += cnt[1]; tot_s += cnt[2]
             evald += 1
-    per_eval = (40.0 * tot_v + 8.0 * nterms * tot_f + 32.0 * tot_s) / max(evald, 1)
+    per_eval = (48.0 * tot_v + 8.0 * nterms * tot_f + 32.0 * tot_s) / max(evald, 1)
     frac_eval = evald / n_sample
     depth = inf["depth"] + 1
     paths = 4 if P["images"] else 2
     commit = paths * depth * nterms * 16.0
-    return dict(per_move=per_eval * frac_eval + commit * 0.9 * frac_eval,
+    return dict(per_move=per_eval * frac_eval + commit * accept,
                 per_eval=per_eval, visited=tot_v / max(evald, 1), far=tot_f / max(evald, 1),
                 near=tot_s / max(evald, 1), eval_fraction=frac_eval, commit_bytes=commit)
 
@@ -459,7 +460,7 @@ def main():
     value = total_moves / res["wall"]
     ms_per_step = 1000.0 * res["wall"] / args.steps
     mc_ms = float(np.mean(res["mc_ms"]))
-    ab = algorithmic_bytes_per_move(c)
+    ab = algorithmic_bytes_per_move(c, accept=res["stats"]["accepted"] / max(res["stats"]["moves"], 1))
     achieved = ab["per_move"] * c["moves"] / (mc_ms / 1000.0) / 1e9
     g = GATED_CHAIN
     out = {

@@ -907,57 +907,70 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
     // lane per leaf taking that leaf's operations in order; moves between leaves are independent.
     // A source that fills a hole and leaves the leaf later in the round has its slot followed in
     // op_slot; its final tracking is written by the lane of the leaf it moves to.
-    if (tid < 4 * kBM) {
+    if (tid < 64) {
+        // lane o < 4 kBM holds operation o; the loops below walk the operations in order, the
+        // same for every lane, reading each one's fields from its lane
         const int o = tid;
-        const int cell = MV.op_cell[o];
-        bool lead = MV.op_type[o] != 0;
-        for (int o2 = 0; o2 < o && lead; ++o2)
-            if (MV.op_type[o2] != 0 && MV.op_cell[o2] == cell) lead = false;
-        if (lead) {
-            const int base = MV.op_base[o];
-            int count = MV.op_count[o];
-            for (int o2 = o; o2 < 4 * kBM; ++o2) {
-                const int type = MV.op_type[o2];
-                if (type == 0 || MV.op_cell[o2] != cell) continue;
-                const int src = MV.op_src[o2];
-                const double4 nv = MV.ct[o2 >> 2][(o2 & 3) == 0 || (o2 & 3) == 1 ? 1 : 3];
-                if (type == 2) {  // append
-                    R.pool4[base + count] = nv;
-                    R.pidx[base + count] = src;
-                    R.track[src] = make_int2(cell, count);
-                    ++count;
-                } else {
-                    const int k = MV.op_slot[o2];
-                    if (type == 3) {  // the source stays in this leaf: new position in place
-                        R.pool4[base + k] = nv;
-                    } else {          // delete: the last entry fills the hole
-                        const int last = count - 1;
-                        if (k != last) {
-                            const int moved = R.pidx[base + last];
-                            const double4 mv = R.pool4[base + last];
-                            R.pool4[base + k] = mv;
-                            R.pidx[base + k] = moved;
-                            bool leaves_later = false;
-                            for (int o3 = o2 + 1; o3 < 4 * kBM; ++o3)
-                                if (MV.op_cell[o3] == cell && (MV.op_type[o3] == 1 || MV.op_type[o3] == 3) &&
-                                    MV.op_src[o3] == moved) {
-                                    MV.op_slot[o3] = k;
-                                    leaves_later = MV.op_type[o3] == 1;
-                                }
-                            if (moved < 0 || moved >= R.nsrc) MV.err = kErrCommitSource;
-                            else if (!leaves_later) R.track[moved] = make_int2(cell, k);
-                        }
-                        count = last;
-                    }
-                }
-                if (type != 1) R.src[src] = nv;
-            }
-            R.cm[cell].x = count;
+        const bool has = o < 4 * kBM;
+        const int my_type = has ? MV.op_type[o] : 0;
+        const int my_cell = has ? MV.op_cell[o] : -1;
+        const int my_src = has ? MV.op_src[o] : -1;
+        const int base = has ? MV.op_base[o] : 0;
+        int count = has ? MV.op_count[o] : 0;
+        bool lead = my_type != 0;
+#pragma unroll
+        for (int o2 = 0; o2 < 4 * kBM; ++o2) {
+            const int t2 = __builtin_amdgcn_readlane(my_type, o2), c2 = __builtin_amdgcn_readlane(my_cell, o2);
+            if (o2 < o && t2 != 0 && c2 == my_cell) lead = false;
         }
+        bool touched = false;  // an earlier operation of the round has changed this leaf
+        for (int o2 = 0; o2 < 4 * kBM; ++o2) {
+            const int type = __builtin_amdgcn_readlane(my_type, o2);
+            if (type == 0) continue;  // uniform
+            const int cell = __builtin_amdgcn_readlane(my_cell, o2);
+            const int src = __builtin_amdgcn_readlane(my_src, o2);
+            if (!lead || cell != my_cell) continue;
+            const double4 nv = MV.ct[o2 >> 2][(o2 & 3) == 0 || (o2 & 3) == 1 ? 1 : 3];
+            if (type == 2) {  // append
+                R.pool4[base + count] = nv;
+                R.pidx[base + count] = src;
+                R.track[src] = make_int2(cell, count);
+                ++count;
+            } else {
+                const int k = MV.op_slot[o2];
+                if (type == 3) {  // the source stays in this leaf: new position in place
+                    R.pool4[base + k] = nv;
+                } else {          // delete: the last entry fills the hole
+                    const int last = count - 1;
+                    if (k != last) {
+                        // untouched, the leaf is as it was when its last entry was prefetched
+                        const int jb = o2 >> 2, jj = (o2 & 3) >> 1;
+                        const int moved = touched ? R.pidx[base + last] : MV.last_pidx[jb][jj];
+                        const double4 mv = touched ? R.pool4[base + last] : MV.last_pool[jb][jj];
+                        R.pool4[base + k] = mv;
+                        R.pidx[base + k] = moved;
+                        bool leaves_later = false;
+                        for (int o3 = o2 + 1; o3 < 4 * kBM; ++o3)
+                            if (MV.op_cell[o3] == cell && (MV.op_type[o3] == 1 || MV.op_type[o3] == 3) &&
+                                MV.op_src[o3] == moved) {
+                                MV.op_slot[o3] = k;
+                                leaves_later = MV.op_type[o3] == 1;
+                            }
+                        if (moved < 0 || moved >= R.nsrc) MV.err = kErrCommitSource;
+                        else if (!leaves_later) R.track[moved] = make_int2(cell, k);
+                    }
+                    count = last;
+                }
+            }
+            if (type != 1) R.src[src] = nv;
+            touched = true;
+        }
+        if (lead) R.cm[my_cell].x = count;
     }
-    // ---- meanwhile: distinct cells of the accepted moves' root paths, in (move, contribution)
-    // order, each with the contributions that apply to it
-    for (int it = tid; it < ndone * 4 * kMaxLevels; it += BLOCK) {
+    // ---- meanwhile, on the other waves: distinct cells of the accepted moves' root paths, in
+    // (move, contribution) order, each with the contributions that apply to it
+    for (int it = tid - 64; it < ndone * 4 * kMaxLevels; it += BLOCK - 64) {
+        if (it < 0) break;  // the first wave (leaf index arrays above)
         const int j = it / (4 * kMaxLevels), cc = (it / kMaxLevels) & 3, l = it % kMaxLevels;
         if (!MV.acc[j] || cc >= nps || l >= MV.plen[j][cc]) continue;
         const int c = MV.path[j][cc][l];
@@ -986,14 +999,18 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
     // of each path entry's offset from its cell centre are tabulated first (in the traversal's
     // list space), so a term is three table reads per contribution; without room, d^n is
     // formed by repeated multiplication.
-    if (tid == 0) {
-        int rows = 0;
-        for (int jc = 0; jc < 4 * kBM; ++jc) {
-            const int j = jc >> 2, cc = jc & 3;
-            if (j < ndone && MV.acc[j] && cc < nps) { MV.pw_row[jc] = rows; rows += MV.plen[j][cc]; }
-            else MV.pw_row[jc] = -1;
+    if (tid < 64) {  // first power-table row of each path entry: an exclusive scan of the path lengths
+        const int jc = tid, j = jc >> 2, cc = jc & 3;
+        const bool on = jc < 4 * kBM && j < ndone && MV.acc[j] && cc < nps;
+        const int len = on ? MV.plen[j][cc] : 0;
+        int x = len;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (tid >= off) x += y;
         }
-        MV.pw_rows = rows;
+        if (jc < 4 * kBM) MV.pw_row[jc] = on ? x - len : -1;
+        if (tid == 63) MV.pw_rows = x;
     }
     __syncthreads();
     const bool use_pw = MV.pw_rows <= BTrav<BLOCK>::PWROWS;
