@@ -230,7 +230,9 @@ def accuracy(P, x, y, z, q):
     return {"E_4_1": e41, "E_rel": erel, "E_tree": E_tree, "E_direct": E_dir, "meets_1e-4": max(e41, erel) <= 1e-4}
 
 
-def run_batched(R, sweeps, params, seed=0):
+def timed_sweeps(R, sweeps, params, seed=0):
+    """One autotuned handle of the R replicas: a warm-up sweep (which builds the graph),
+    then `sweeps` timed sweeps; and the accuracy on the smallest, median and largest replica."""
     import torch
     from paper_1305_1825_amd import bhmc, workloads as W
     sizes = [int(v) for v in W.replica_sizes(R, seed=seed)]
@@ -240,7 +242,7 @@ def run_batched(R, sweeps, params, seed=0):
            for k in range(1, 5)]
     t = bhmc.Tree(Ps, *cat, n_per_replica=sizes)
     tune = t.autotune(seed=seed, step=1.0, trial_moves=2000)
-    t.batch_sweep(seed=seed, n_sweeps=1, step=1.0, use_graph=True)  # warm-up sweep, builds the graph
+    t.batch_sweep(seed=seed, n_sweeps=1, step=1.0, use_graph=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = t.batch_sweep(seed=seed, n_sweeps=sweeps, step=1.0, use_graph=True)
@@ -256,17 +258,32 @@ def run_batched(R, sweeps, params, seed=0):
         P, x, y, z, q = reps[r]
         a = accuracy(Ps[r], x, y, z, q)
         acc.append(dict(replica=r, n=sizes[r], **{k: a[k] for k in ("E_4_1", "E_rel", "meets_1e-4")}))
+    return dict(moves=moves, wall=wall, rebuilds=rebuilds, autotune=tune, accuracy=acc, sizes=sizes, reps=reps, Ps=Ps,
+                order=order)
+
+
+def run_batched(R, sweeps, params, seed=0, far32=True):
+    sw = timed_sweeps(R, sweeps, params, seed)
+    moves, wall, rebuilds, tune, acc = sw["moves"], sw["wall"], sw["rebuilds"], sw["autotune"], sw["accuracy"]
+    sizes, reps, Ps, order = sw["sizes"], sw["reps"], sw["Ps"], sw["order"]
     # the plain single-chain kernel on one median replica, same parameters, as many moves as one
     # of its sweeps
     rm = order[R // 2]
     P, x, y, z, q = reps[rm]
     plain = chain_kernel_rate(Ps[rm], x, y, z, q, moves=sizes[rm], seed=seed, replica=0)
     rounds = chain_kernel_rate(Ps[rm], x, y, z, q, moves=sizes[rm], seed=seed, replica=0, moves_per_round=0)
-    return dict(moves=moves, wall=wall, moves_per_s=moves / wall, replicas=R, sweeps=sweeps, rebuilds=rebuilds,
-                n_min=min(sizes), n_max=max(sizes), n_total=sum(sizes), autotune=tune, params=params,
-                accuracy=acc, plain_median_replica=dict(replica=rm, n=sizes[rm], **plain),
-                rounds_median_replica=dict(replica=rm, n=sizes[rm], **rounds),
-                ratio_vs_plain=(moves / wall) / plain["moves_per_s"])
+    out = dict(moves=moves, wall=wall, moves_per_s=moves / wall, replicas=R, sweeps=sweeps, rebuilds=rebuilds,
+               n_min=min(sizes), n_max=max(sizes), n_total=sum(sizes), autotune=tune, params=params,
+               accuracy=acc, plain_median_replica=dict(replica=rm, n=sizes[rm], **plain),
+               rounds_median_replica=dict(replica=rm, n=sizes[rm], **rounds),
+               ratio_vs_plain=(moves / wall) / plain["moves_per_s"])
+    if far32:
+        # the same sweeps with the single-precision far field (FP64 sums), gated the same way
+        f = timed_sweeps(R, sweeps, dict(params, far_fp32=1), seed)
+        out["far_fp32"] = dict(moves_per_s=f["moves"] / f["wall"], moves=f["moves"], wall=f["wall"],
+                               autotune=f["autotune"], accuracy=f["accuracy"],
+                               gate_met=all(a["meets_1e-4"] for a in f["accuracy"]))
+    return out
 
 
 def run_gradient(theta=0.5, calls=3):
@@ -513,6 +530,18 @@ def main():
         out["stated_theta05_p6"] = {"moves_per_s": cs["moves"] / (rs["mc_ms"][0] / 1000.0),
                                     **{k: v for k, v in accuracy(cs["params"], cs["x"], cs["y"], cs["z"],
                                                                  cs["q"]).items() if k != "E_tree"}}
+    if not args.no_stated:
+        log("the headline chain with the single-precision far field")
+        cf = dict(c, params=dict(c["params"], far_fp32=1))
+        rf = run_plain(cf, 1, 0, tune=False)
+        ff = rf["final"]
+        a0, a1 = accuracy(cf["params"], c["x"], c["y"], c["z"], c["q"]), accuracy(cf["params"], *ff)
+        out["far_fp32_chain"] = {
+            "moves_per_s": c["moves"] / (rf["mc_ms"][0] / 1000.0),
+            "note": "far cells evaluated in FP32 from an FP32 copy of the moments, every sum in FP64",
+            "accuracy_start": {k: a0[k] for k in ("E_4_1", "E_rel", "meets_1e-4")},
+            "accuracy_end": {k: a1[k] for k in ("E_4_1", "E_rel", "meets_1e-4")},
+            "gate_met": a0["meets_1e-4"] and a1["meets_1e-4"]}
     if not args.no_batched:
         log("batched replicas")
         b = run_batched(256, args.batched_sweeps, GATED_REPLICAS)
