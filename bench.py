@@ -44,7 +44,11 @@ GATED_REPLICAS = dict(theta=0.3, p=5, n0=0)
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
 # counters on a plain device copy), valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "csrc": None,
+    "csrc": "97983ae113ae",
+    "chain": {"units": 100000, "bytes": 182604140},        # eval_p5::k_mcb<512>, 10^5 moves
+    "sweep": {"units": 3038540, "bytes": 1.0160e12},       # eval_p5::k_mcb<512>, one sweep of 256 replicas
+    "sweep_fp32": {"units": 3038540, "bytes": 5.941e11},   # the same with the single-precision far field
+    "grad": {"units": 1, "bytes": 1.1575e10},              # eval_p6::k_grad, one call at 10^5 ions
 }
 
 
@@ -282,7 +286,8 @@ def run_batched(R, sweeps, params, seed=0, far32=True):
         f = timed_sweeps(R, sweeps, dict(params, far_fp32=1), seed)
         out["far_fp32"] = dict(moves_per_s=f["moves"] / f["wall"], moves=f["moves"], wall=f["wall"],
                                autotune=f["autotune"], accuracy=f["accuracy"],
-                               gate_met=all(a["meets_1e-4"] for a in f["accuracy"]))
+                               gate_met=all(a["meets_1e-4"] for a in f["accuracy"]),
+                               traffic=traffic("sweep_fp32", f["moves"] // sweeps))
     return out
 
 
