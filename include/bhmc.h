@@ -269,7 +269,7 @@ bhmc_status bhmc_energy_grad(bhmc_tree* tree, int32_t replica, double* dEdr_dev,
 /* Trial moves evaluated together by bhmc_mc_run and bhmc_batch_sweep (and the
  * autotuner).  moves = 1: one move at a time (evaluate, decide, commit).
  * moves = 0 (the default) or > 1: rounds of up to that many consecutive moves
- * of distinct ions (at most 8 for p <= 6, 4 for p <= 8, 2 above), evaluated in
+ * of distinct ions (at most 8 for p <= 8, 2 above), evaluated in
  * one traversal of the tree as it stands at the start of the round and then
  * decided and committed in order, each energy change corrected exactly for the
  * moves accepted before it in the round (Sec. 3.2 with N_0 = 0: the
@@ -287,7 +287,9 @@ bhmc_status bhmc_set_moves_per_round(bhmc_tree* tree, int32_t moves, int32_t* ef
  * handle's expansion order -- set-up, traversal levels, corrected moments and
  * scan, far cells, near leaves, hard cores below far cells, path descents,
  * corrections, decisions, leaf index arrays, moments -- then the number of
- * rounds and of moves.  ticks: host, n values; count (nullable, host) receives
+ * rounds and of moves, the level loop's chunks, frontier entries, empty
+ * entries, far and near list entries, and the ticks the root-path descents
+ * and the commit prefetch spend inside the level loop.  ticks: host, n values; count (nullable, host) receives
  * the number of counters (0 for a library built without timers, which then
  * writes nothing).  reset = 1 clears them after reading. */
 bhmc_status bhmc_phase_ticks(bhmc_tree* tree, uint64_t* ticks, int32_t n, int32_t reset, int32_t* count);

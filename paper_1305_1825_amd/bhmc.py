@@ -273,7 +273,7 @@ class Tree:
 
     PHASES = ("setup", "levels", "flagged_scan", "far", "near", "overlap", "paths", "corrections", "decisions",
               "slots", "moments", "rounds", "moves", "chunks", "entries", "empty_entries", "far_entries",
-              "near_entries")
+              "near_entries", "hook_paths", "hook_prefetch")
 
     def phase_ticks(self, reset=True):
         """Phase timers of the batched kernel (a library built with phase timers), else {}."""

@@ -24,7 +24,7 @@
 // their root paths with the contributions applied in move order.  Every result is
 // the one the move-by-move chain gives, up to the rounding of the sums.
 
-constexpr int kBM = P <= 6 ? 8 : (P <= 8 ? 4 : 2);  // trial moves per round (LDS for corrected moments)
+constexpr int kBM = P <= 8 ? 8 : 2;  // trial moves per round (LDS: p = 8 with 8 moves just fits 160 KB)
 constexpr int kBT = 2 * kBM;                         // targets per round: 2b old, 2b + 1 new position
 // frontier / list entry: cell (bits 0-23), move (24-26), mask of the move's two targets (27-28),
 // the cell holds the move's own ion (29) or image (30)
@@ -41,7 +41,9 @@ static_assert(kBM <= 8, "the move index has three bits");
 enum { kPhSetup = 0, kPhLevels, kPhFlagged, kPhFar, kPhNear, kPhOverlap, kPhPaths, kPhCorr, kPhDecide,
        kPhSlots, kPhMoments, kPhRounds, kPhMoves,
        // counts: level-loop chunks, frontier entries, entries holding no remaining source, far and near list entries
-       kPhChunks, kPhEntries, kPhEmpty, kPhFarN, kPhNearN, kNumPhases };
+       kPhChunks, kPhEntries, kPhEmpty, kPhFarN, kPhNearN,
+       // ticks inside the traversal (overlapping the level loop): path descents, commit prefetch
+       kPhHookPath, kPhHookPf, kNumPhases };
 #ifdef BHMC_PHASE_TIMERS
 __device__ unsigned long long g_phase[kNumPhases];
 #define PHASE_START() long long ph_t0_ = wall_clock64()
@@ -702,10 +704,20 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
         }
     };
     auto hook = [&](int) {
+#ifdef BHMC_PHASE_TIMERS
+        const long long hk0 = wall_clock64();
+#endif
         if (path_lane)
             for (int k = 0; k < 2 && MV.plen[pb][pj] == 0 && my_level < kMaxLevels; ++k) step(my_level++);
+#ifdef BHMC_PHASE_TIMERS
+        const long long hk1 = wall_clock64();
+        if (th == 0) atomicAdd(&g_phase[kPhHookPath], (unsigned long long)(hk1 - hk0));
+#endif
         if (pf_lane)
             for (int k = 0; k < 2; ++k) prefetch_stage_mb(R, MV, tp >> 1, tp & 1);
+#ifdef BHMC_PHASE_TIMERS
+        if (tp == 0) atomicAdd(&g_phase[kPhHookPf], (unsigned long long)(wall_clock64() - hk1));
+#endif
     };
     PHASE(kPhSetup);
     traverse_mb<BLOCK>(R, S, MV, hook);

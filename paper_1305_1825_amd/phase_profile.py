@@ -9,7 +9,8 @@ microseconds per round and per trial move of each phase: set-up, traversal
 levels, corrected moments and scan, far cells, near leaves, hard cores below far
 cells, path descents, corrections, decisions, leaf index arrays and moments;
 and per round the traversal's chunks of frontier entries, its entries (and how
-many hold no source besides the movers'), and its far and near list entries.
+many hold no source besides the movers'), its far and near list entries, and the
+time the root-path descents and the commit prefetch take inside the level loop.
 
     python -m paper_1305_1825_amd.phase_profile [--moves 20000] [--no-sweep]
 """
@@ -30,15 +31,21 @@ from . import workloads as W  # noqa: E402
 CLOCK_HZ = 100e6  # the device's constant clock read by wall_clock64
 # counters rather than ticks: level-loop chunks, frontier entries, entries with no remaining source, list entries
 COUNTS = ("chunks", "entries", "empty_entries", "far_entries", "near_entries")
+# ticks spent inside the traversal's level loop by the waves that also descend the root paths and
+# prefetch the commit state (they overlap the level time, so they are not added to the sum)
+OVERLAPPED = ("hook_paths", "hook_prefetch")
 
 
 def report(name, ticks, wall_s=None):
     rounds, moves = ticks.get("rounds", 0), ticks.get("moves", 0)
     out = {"workload": name, "rounds": rounds, "moves": moves}
     if rounds:
-        timed = {k: v for k, v in ticks.items() if k not in ("rounds", "moves") + COUNTS}
+        timed = {k: v for k, v in ticks.items() if k not in ("rounds", "moves") + COUNTS + OVERLAPPED}
         for k, v in timed.items():
             out[k + "_us_per_round"] = v / CLOCK_HZ * 1e6 / rounds
+        for k in OVERLAPPED:
+            if k in ticks:
+                out[k + "_us_per_round_within_levels"] = ticks[k] / CLOCK_HZ * 1e6 / rounds
         out["sum_us_per_round"] = sum(timed.values()) / CLOCK_HZ * 1e6 / rounds
         for k in COUNTS:
             if k in ticks:
