@@ -37,7 +37,9 @@ constexpr int kChunk = 2;  // frontier entries per lane per chunk of the travers
 static_assert(kBM <= 8, "the move index has three bits");
 
 // Phase timers of a round (built with -DBHMC_PHASE_TIMERS only): thread 0 adds the
-// constant-clock ticks of each phase to a device array read by bhmc_phase_ticks.
+// constant-clock ticks of each phase, and the level loop its counts, to the workgroup's
+// accumulators in LDS (no device atomics on the round's path); a workgroup adds them to
+// the device array read by bhmc_phase_ticks when it finishes a replica.
 enum { kPhSetup = 0, kPhLevels, kPhFlagged, kPhFar, kPhNear, kPhOverlap, kPhPaths, kPhCorr, kPhDecide,
        kPhSlots, kPhMoments, kPhRounds, kPhMoves,
        // counts: level-loop chunks, frontier entries, entries holding no remaining source, far and near list entries
@@ -46,16 +48,17 @@ enum { kPhSetup = 0, kPhLevels, kPhFlagged, kPhFar, kPhNear, kPhOverlap, kPhPath
        kPhHookPath, kPhHookPf, kNumPhases };
 #ifdef BHMC_PHASE_TIMERS
 __device__ unsigned long long g_phase[kNumPhases];
+__shared__ unsigned long long s_phase[kNumPhases];
 #define PHASE_START() long long ph_t0_ = wall_clock64()
 #define PHASE(k)                                                         \
     do {                                                                 \
         if (threadIdx.x == 0) {                                          \
             const long long ph_t1_ = wall_clock64();                     \
-            atomicAdd(&g_phase[k], (unsigned long long)(ph_t1_ - ph_t0_)); \
+            s_phase[k] += (unsigned long long)(ph_t1_ - ph_t0_);         \
             ph_t0_ = ph_t1_;                                             \
         }                                                                \
     } while (0)
-#define PHASE_COUNT(k, v) do { if (threadIdx.x == 0) atomicAdd(&g_phase[k], (unsigned long long)(v)); } while (0)
+#define PHASE_COUNT(k, v) do { if (threadIdx.x == 0) s_phase[k] += (unsigned long long)(v); } while (0)
 #else
 #define PHASE_START() do {} while (0)
 #define PHASE(k) do {} while (0)
@@ -415,10 +418,10 @@ __device__ void traverse_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, Hook&& ho
                 {
                     const uint64_t bv = __ballot(valid[h]), be = __ballot(valid[h] && m[h].x - fi - fk <= 0);
                     if (lane == 0) {
-                        atomicAdd(&g_phase[kPhEntries], (unsigned long long)__popcll(bv));
-                        atomicAdd(&g_phase[kPhEmpty], (unsigned long long)__popcll(be));
-                        atomicAdd(&g_phase[kPhFarN], (unsigned long long)(__popcll(bf[h]) + __popcll(bg[h])));
-                        atomicAdd(&g_phase[kPhNearN], (unsigned long long)__popcll(bn[h]));
+                        atomicAdd(&s_phase[kPhEntries], (unsigned long long)__popcll(bv));
+                        atomicAdd(&s_phase[kPhEmpty], (unsigned long long)__popcll(be));
+                        atomicAdd(&s_phase[kPhFarN], (unsigned long long)(__popcll(bf[h]) + __popcll(bg[h])));
+                        atomicAdd(&s_phase[kPhNearN], (unsigned long long)__popcll(bn[h]));
                     }
                 }
 #endif
@@ -711,12 +714,12 @@ __device__ RoundOut round_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, int b0, 
             for (int k = 0; k < 2 && MV.plen[pb][pj] == 0 && my_level < kMaxLevels; ++k) step(my_level++);
 #ifdef BHMC_PHASE_TIMERS
         const long long hk1 = wall_clock64();
-        if (th == 0) atomicAdd(&g_phase[kPhHookPath], (unsigned long long)(hk1 - hk0));
+        if (th == 0) atomicAdd(&s_phase[kPhHookPath], (unsigned long long)(hk1 - hk0));
 #endif
         if (pf_lane)
             for (int k = 0; k < 2; ++k) prefetch_stage_mb(R, MV, tp >> 1, tp & 1);
 #ifdef BHMC_PHASE_TIMERS
-        if (tp == 0) atomicAdd(&g_phase[kPhHookPf], (unsigned long long)(wall_clock64() - hk1));
+        if (tp == 0) atomicAdd(&s_phase[kPhHookPf], (unsigned long long)(wall_clock64() - hk1));
 #endif
     };
     PHASE(kPhSetup);
@@ -1099,6 +1102,9 @@ __global__ void __launch_bounds__(BLOCK) k_mcb(Rep* reps, McArgs A) {
     __shared__ int s_r;
     const int tid = threadIdx.x;
     for (int k = tid; k < NTERM; k += BLOCK) S.mi[k] = mi_code(k);
+#ifdef BHMC_PHASE_TIMERS
+    for (int k = tid; k < kNumPhases; k += BLOCK) s_phase[k] = 0;
+#endif
     const int bmax = A.bm > 0 && A.bm < kBM ? A.bm : kBM;
     for (;;) {
         if (tid == 0) {
@@ -1157,6 +1163,12 @@ __global__ void __launch_bounds__(BLOCK) k_mcb(Rep* reps, McArgs A) {
             if (detail) gr->err_detail = detail;
             gr->stats[0] += st_moves; gr->stats[1] += st_acc; gr->stats[2] += st_wall;
             gr->stats[3] += st_ovl; gr->stats[4] += st_met;
+#ifdef BHMC_PHASE_TIMERS
+            for (int k = 0; k < kNumPhases; ++k) {
+                atomicAdd(&g_phase[k], s_phase[k]);
+                s_phase[k] = 0;
+            }
+#endif
         }
         __syncthreads();
     }
