@@ -87,6 +87,19 @@ enum { BHMC_REASON_NONE = 0, BHMC_REASON_WALL = 1, BHMC_REASON_OVERLAP = 2 };
  *              this adds is at most about (C(p+3,3) + 3p + 4) 2^-24 times the
  *              far field's magnitude sum_A sum_n |T_n M_A^n|.  The gradient is
  *              always FP64.  0: everything in FP64.
+ *   line_images 0, or M in 1..8 (needs images = 1, n0 = 0, eps_in <= eps_out):
+ *              the multiple-image model of the dielectric sphere that the paper
+ *              names in Sec. 1 and Sec. 5.  The exact reaction potential of a
+ *              charge outside the sphere is that of the Kelvin image plus a line
+ *              of charge from the centre to the Kelvin point r_K, of density
+ *              -sigma q_K t^(sigma-1) at t r_K (t in [0, 1], sigma =
+ *              eps_out / (eps_in + eps_out)); the line is replaced by the M-point
+ *              Gauss rule of the weight t^(sigma-1) on [0, 1] (nodes t_m and
+ *              weights w_m rounded to multiples of 2^-40): M more sources per
+ *              ion, -sigma w_m q_K at t_m r_K, numbered 2n + m n + i.  Only
+ *              bhmc_energy and bhmc_energy_noalloc evaluate it; the Monte Carlo,
+ *              energy change, commit and gradient calls return BHMC_EINVAL.
+ *   reserved   0.
  */
 typedef struct {
     double l_B;
@@ -106,6 +119,8 @@ typedef struct {
     double hard_core;
     int32_t slot_slack;
     int32_t far_fp32;
+    int32_t line_images;
+    int32_t reserved;   /* 0 */
 } bhmc_params;
 
 /* Statistics of a Monte Carlo run, summed over the moves it made. */
@@ -123,7 +138,7 @@ typedef struct bhmc_tree bhmc_tree;
 /* Tree geometry summary for one replica. */
 typedef struct {
     int64_t n;        /* ions                                                 */
-    int64_t nsrc;     /* sources: n, or 2n with images                        */
+    int64_t nsrc;     /* sources: n, or (2 + line_images) n with images       */
     int64_t ncell;
     int64_t nleaf;
     int64_t nterms;   /* (p+1)(p+2)(p+3)/6 moments per cell                   */

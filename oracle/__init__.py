@@ -26,7 +26,7 @@ ORC_PARAM_FIELDS = [
     ("box_lo", C.c_double * 3), ("box_side", C.c_double),
     ("a", C.c_double), ("Q_center", C.c_double), ("eps_in", C.c_double), ("eps_out", C.c_double),
     ("r_min", C.c_double), ("r_max", C.c_double), ("hard_core", C.c_double),
-    ("slot_slack", C.c_int32), ("_pad", C.c_int32),
+    ("slot_slack", C.c_int32), ("line_images", C.c_int32),
 ]
 
 
@@ -99,6 +99,7 @@ def _declare(L):
         "orc_taylor": (None, [C.c_int, C.c_double, C.c_double, C.c_double, _d]),
         "orc_multi_indices": (None, [C.c_int, _i32]),
         "orc_tree_certificate": (C.c_double, [_T, _d, C.POINTER(C.c_int), C.c_int]),
+        "orc_line_rule": (C.c_int, [C.c_double, C.c_int, _d, _d]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -109,7 +110,8 @@ def _declare(L):
 def params(d: dict) -> OrcParams:
     p = OrcParams()
     for name, _ in ORC_PARAM_FIELDS:
-        if name == "_pad":
+        if name == "line_images":
+            p.line_images = int(d.get("line_images", 0))
             continue
         v = d[name]
         if name == "box_lo":
@@ -152,6 +154,16 @@ def kelvin(a, gamma, x, y, z, q):
     out = np.zeros(4)
     lib().orc_kelvin(a, gamma, x, y, z, q, _ptr(out, _d))
     return out
+
+
+def line_rule(sigma, M):
+    """Nodes and weights of the M-point Gauss rule for the weight t^(sigma - 1) on
+    [0, 1] (the line image of the multiple-image model)."""
+    t = np.zeros(8)
+    w = np.zeros(8)
+    if lib().orc_line_rule(float(sigma), int(M), _ptr(t, _d), _ptr(w, _d)) != 0:
+        raise ValueError("line rule needs 1 <= M <= 8 and 1/2 <= sigma <= 1")
+    return t[:M].copy(), w[:M].copy()
 
 
 def keys(P: dict, x, y, z):

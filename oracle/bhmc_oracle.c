@@ -23,7 +23,11 @@
  *   - Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the Metropolis
  *     driver (Sec. 2, steps 1-3; Sec. 3.3);
  *   - the treecode energy and its exact gradient, summed pair by pair over the
- *     interaction lists the traversal produces.
+ *     interaction lists the traversal produces;
+ *   - the multiple-image model of the dielectric sphere (Sec. 1 and Sec. 5
+ *     name it without formulas): besides the Kelvin image, a line image from
+ *     the sphere's centre to the Kelvin point, discretised by a Gauss-Jacobi
+ *     rule; energies only.
  *
  * Every floating-point expression whose outcome decides an integer (a key, a
  * MAC decision, a wall or overlap test, a Metropolis decision) is written left
@@ -56,7 +60,7 @@ typedef struct {
     double r_min, r_max; /* shell confinement (Sec. 4, spherical cell model)  */
     double hard_core;    /* contact distance tau (eq. 2.1)                    */
     int32_t slot_slack;  /* leaf slots = slack * max(count, leaf_cap) + 2    */
-    int32_t _pad;
+    int32_t line_images; /* 0, or M line-image points per ion (energies only) */
 } orc_params;
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOUTSIDE = -2, ORC_ECAPACITY = -6 };
@@ -196,6 +200,105 @@ void orc_kelvin(double a, double gamma, double x, double y, double z, double q, 
     out[3] = ((gamma * a) * q) / rn;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Multiple images                                                          */
+/*                                                                          */
+/* A unit charge at y outside the sphere (|y| > a, eps_in inside, eps_out   */
+/* outside) has the reaction potential, outside,                            */
+/*   G_R(x; y) = sum_n b_n a^(2n+1) / (|y|^(n+1) |x|^(n+1)) P_n(cos angle), */
+/*   b_n = n (eps_out - eps_in) / (n eps_in + (n + 1) eps_out)              */
+/*       = gamma n / (n + sigma),  sigma = eps_out / (eps_in + eps_out).    */
+/* With n / (n + sigma) = 1 - sigma int_0^1 t^(n + sigma - 1) dt this is    */
+/* the Kelvin image gamma a / |y| at y_K = a^2 y / |y|^2 plus a line of      */
+/* charge -sigma (gamma a / |y|) t^(sigma - 1) dt at t y_K, t in [0, 1].      */
+/* The line is replaced by M points: the Gauss rule of the weight           */
+/* t^(sigma - 1) on [0, 1].                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Jacobi polynomial P_n^(0, b)(x) and its derivative, by the three-term
+ * recurrence in n. */
+static void jacobi0b(int n, double b, double x, double *p, double *dp) {
+    double p0 = 1.0, p1 = 0.5 * (-b + (b + 2.0) * x);
+    if (n == 0) { *p = 1.0; *dp = 0.0; return; }
+    for (int k = 2; k <= n; ++k) {
+        double c = 2.0 * k + b;
+        double a1 = 2.0 * k * (k + b) * (c - 2.0);
+        double a2 = (c - 1.0) * (-b * b);
+        double a3 = (c - 1.0) * c * (c - 2.0);
+        double a4 = 2.0 * (k - 1.0) * (k + b - 1.0) * c;
+        double p2 = ((a2 + a3 * x) * p1 - a4 * p0) / a1;
+        p0 = p1; p1 = p2;
+    }
+    /* (2n + b)(1 - x^2) P_n' = n (-b - (2n + b) x) P_n + 2 n (n + b) P_{n-1} */
+    double c = 2.0 * n + b;
+    *p = p1;
+    *dp = (n * (-b - c * x) * p1 + 2.0 * n * (n + b) * p0) / (c * (1.0 - x * x));
+}
+
+/* Nodes t[0..M) and weights w[0..M) with sum_m w_m f(t_m) = int_0^1 t^(sigma-1) f(t) dt
+ * for every polynomial f of degree < 2M: Newton's method (with the roots
+ * already found divided out) on P_M^(0, sigma - 1)(2t - 1), weights from
+ *   w = 2^(-sigma) Gamma(M+1) Gamma(M+sigma) / (Gamma(M+sigma) M!) 2^sigma / ((1 - x^2) P_M'(x)^2)
+ *     = 1 / ((1 - x^2) P_M'(x)^2)  in x = 2t - 1.
+ * The nodes come out in descending order.  Returns 0, or -1 for M outside 1..8
+ * or sigma outside [1/2, 1]. */
+int orc_line_rule(double sigma, int M, double *t, double *w) {
+    if (M < 1 || M > 8 || !(sigma >= 0.5 && sigma <= 1.0)) return -1;
+    double b = sigma - 1.0, x[8];
+    for (int m = 0; m < M; ++m) {
+        double z = cos(M_PI * (m + 0.75) / (M + 0.5));  /* descending starting points */
+        for (int it = 0; it < 100; ++it) {
+            double p, dp;
+            jacobi0b(M, b, z, &p, &dp);
+            double s = 0.0;
+            for (int k = 0; k < m; ++k) s += 1.0 / (z - x[k]);
+            double dz = p / (dp - p * s);
+            z -= dz;
+            if (fabs(dz) <= 1e-16 * (1.0 + fabs(z))) break;
+        }
+        x[m] = z;
+    }
+    /* nodes and weights rounded to multiples of 2^-40 (about 1e-12, far below the rule's
+     * own error), so that an independent computation of the rule gives the same sources */
+    for (int m = 0; m < M; ++m) {
+        double p, dp;
+        jacobi0b(M, b, x[m], &p, &dp);
+        t[m] = ldexp(nearbyint(ldexp(0.5 * (1.0 + x[m]), 40)), -40);
+        w[m] = ldexp(nearbyint(ldexp(1.0 / ((1.0 - x[m] * x[m]) * dp * dp), 40)), -40);
+    }
+    return 0;
+}
+
+/* sigma = eps_out / (eps_in + eps_out), the exponent of the line image. */
+static double sigma_of(const orc_params *P) { return P->eps_out / (P->eps_in + P->eps_out); }
+
+/* Image kernel K(x, y): the potential at x of the images of a unit charge at y
+ * (both outside the sphere), symmetric in x and y:
+ *   gamma a / sqrt(D_1) - sigma gamma a sum_m w_m / sqrt(D_{t_m}),
+ *   D_t = |y|^2 |x - t y_K|^2 = |x|^2 |y|^2 - 2 t a^2 x.y + t^2 a^4. */
+typedef struct { int M; double sigma, t[8], w[8]; } orc_lines;
+
+static void lines_of(const orc_params *P, orc_lines *L) {
+    L->M = 0;
+    L->sigma = sigma_of(P);
+    if (P->images && P->line_images > 0 && orc_line_rule(L->sigma, P->line_images, L->t, L->w) == 0)
+        L->M = P->line_images;
+}
+
+static double image_kernel(const orc_params *P, const orc_lines *L, double xi, double yi, double zi,
+                           double xj, double yj, double zj) {
+    double a = P->a, a2 = a * a, g = gamma_of(P);
+    double ri2 = xi * xi + yi * yi + zi * zi;
+    double rj2 = xj * xj + yj * yj + zj * zj;
+    double dot = xi * xj + yi * yj + zi * zj;
+    double v = g * a / sqrt(ri2 * rj2 - 2.0 * a2 * dot + a2 * a2);
+    for (int m = 0; m < L->M; ++m) {
+        double tt = L->t[m];
+        v -= L->sigma * L->w[m] * g * a / sqrt(ri2 * rj2 - 2.0 * tt * a2 * dot + tt * tt * a2 * a2);
+    }
+    return v;
+}
+
 /* Hard walls (Sec. 4): a move leaving the cell is rejected. */
 static int outside(const orc_params *P, double x, double y, double z) {
     if (P->geom == 0) {
@@ -267,17 +370,16 @@ double orc_direct_energy(const orc_params *P, int64_t n, const double *x, const 
                          const double *z, const double *q) {
     nsum e = {0, 0};
     int shell = P->geom == 1;
-    double g = gamma_of(P), a = P->a;
+    orc_lines L;
+    lines_of(P, &L);
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = i + 1; j < n; ++j) {
             double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
             nadd(&e, q[i] * q[j] / sqrt(dx * dx + dy * dy + dz * dz));
         }
         if (shell && P->images) {
-            for (int64_t j = 0; j < n; ++j) {
-                double D = img_D(a, x[i], y[i], z[i], x[j], y[j], z[j]);
-                nadd(&e, 0.5 * g * a * q[i] * q[j] / sqrt(D));
-            }
+            for (int64_t j = 0; j < n; ++j)
+                nadd(&e, 0.5 * q[i] * q[j] * image_kernel(P, &L, x[i], y[i], z[i], x[j], y[j], z[j]));
         }
         if (shell && P->Q_center != 0.0)
             nadd(&e, P->Q_center * q[i] / sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]));
@@ -289,6 +391,7 @@ double orc_direct_energy(const orc_params *P, int64_t n, const double *x, const 
  * summed (Sec. 1: V_i evaluated at the old and the new position). */
 double orc_direct_delta(const orc_params *P, int64_t n, const double *x, const double *y,
                         const double *z, const double *q, int64_t i, const double *rn) {
+    if (P->line_images) return NAN;  /* the multiple-image model: energies only */
     nsum e = {0, 0};
     int shell = P->geom == 1;
     double g = gamma_of(P), a = P->a;
@@ -324,14 +427,15 @@ double orc_direct_delta(const orc_params *P, int64_t n, const double *x, const d
 void orc_direct_phi(const orc_params *P, int64_t n, const double *x, const double *y,
                     const double *z, const double *q, double *phi) {
     int imgs = P->geom == 1 && P->images;
-    double g = gamma_of(P), a = P->a;
+    orc_lines L;
+    lines_of(P, &L);
     for (int64_t i = 0; i < n; ++i) {
         nsum e = {0, 0};
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
             double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
             nadd(&e, q[j] / sqrt(dx * dx + dy * dy + dz * dz));
-            if (imgs) nadd(&e, g * a * q[j] / sqrt(img_D(a, x[i], y[i], z[i], x[j], y[j], z[j])));
+            if (imgs) nadd(&e, q[j] * image_kernel(P, &L, x[i], y[i], z[i], x[j], y[j], z[j]));
         }
         phi[i] = nval(&e);
     }
@@ -341,6 +445,7 @@ void orc_direct_phi(const orc_params *P, int64_t n, const double *x, const doubl
 void orc_direct_grad(const orc_params *P, int64_t n, const double *x, const double *y,
                      const double *z, const double *q, double *gx, double *gy, double *gz,
                      double *gq) {
+    if (P->line_images) return;  /* the multiple-image model: energies only */
     int shell = P->geom == 1, imgs = shell && P->images;
     double g = gamma_of(P), a = P->a, a2 = a * a;
     for (int64_t i = 0; i < n; ++i) {
@@ -519,6 +624,8 @@ static int validate(const orc_params *P, int64_t n, const double *x, const doubl
         !(P->box_side > 0.0) || P->n0 < 0)
         return ORC_EINVAL;
     if (P->images && P->geom != 1) return ORC_EINVAL;
+    if (P->line_images < 0 || P->line_images > 8 || (P->line_images && !P->images)) return ORC_EINVAL;
+    if (P->line_images && !(sigma_of(P) >= 0.5 && sigma_of(P) <= 1.0)) return ORC_EINVAL;
     if (P->geom == 1) /* the root cube must contain the shell |r| < r_max */
         for (int d = 0; d < 3; ++d)
             if (!(P->box_lo[d] <= -P->r_max && P->box_lo[d] + P->box_side >= P->r_max)) return ORC_EINVAL;
@@ -551,7 +658,7 @@ int orc_tree_build(const orc_params *P, int64_t n, const double *x, const double
     t->gamma = gamma_of(P);
     t->theta2 = P->theta * P->theta;
     t->n = (int)n;
-    t->nsrc = P->images ? 2 * (int)n : (int)n;
+    t->nsrc = P->images ? (2 + P->line_images) * (int)n : (int)n;
     t->nterms = nterms_of(P->p);
     t->pmax1 = P->p + 1;
     int ns = t->nsrc;
@@ -559,11 +666,19 @@ int orc_tree_build(const orc_params *P, int64_t n, const double *x, const double
     t->z = (double *)malloc(sizeof(double) * ns); t->q = (double *)malloc(sizeof(double) * ns);
     for (int i = 0; i < n; ++i) { t->x[i] = x[i]; t->y[i] = y[i]; t->z[i] = z[i]; t->q[i] = q[i]; }
     if (P->images) {
+        orc_lines L;
+        lines_of(P, &L);
         for (int i = 0; i < n; ++i) {
             double im[4];
             orc_kelvin(P->a, t->gamma, x[i], y[i], z[i], q[i], im);
             t->x[n + i] = im[0]; t->y[n + i] = im[1]; t->z[n + i] = im[2]; t->q[n + i] = im[3];
             if (!in_root(P, im[0], im[1], im[2])) { orc_tree_free(t); return ORC_EOUTSIDE; }
+            /* line images of ion i: source 2n + m n + i, charge -sigma w_m q_K at t_m r_K */
+            for (int m = 0; m < L.M; ++m) {
+                int s = 2 * (int)n + m * (int)n + i;
+                t->x[s] = L.t[m] * im[0]; t->y[s] = L.t[m] * im[1]; t->z[s] = L.t[m] * im[2];
+                t->q[s] = -L.sigma * L.w[m] * im[3];
+            }
         }
     }
     t->mi = (int *)malloc(sizeof(int) * 3 * nterms_of(P->p + 1));
@@ -731,6 +846,7 @@ static int overlaps(const otree *t, int64_t i, const double *rn) {
  * has dE = +inf and a reason code. */
 double orc_tree_delta(otree *t, int64_t i, const double *rn, int *reason, int64_t *counts) {
     *reason = REASON_NONE;
+    if (t->P.line_images) return NAN;  /* the multiple-image model: energies only */
     memset(&t->cnt, 0, sizeof(t->cnt));
     if (outside(&t->P, rn[0], rn[1], rn[2])) { *reason = REASON_WALL; return INFINITY; }
     if (overlaps(t, i, rn)) { *reason = REASON_OVERLAP; return INFINITY; }
@@ -818,7 +934,7 @@ static void move_source(otree *t, int s, double xn, double yn, double zn, double
 
 /* Commit an accepted move of ion i to rn: the ion, then its image. */
 int orc_tree_commit(otree *t, int64_t i, const double *rn) {
-    if (i < 0 || i >= t->n) return ORC_EINVAL;
+    if (i < 0 || i >= t->n || t->P.line_images) return ORC_EINVAL;
     if (outside(&t->P, rn[0], rn[1], rn[2])) return ORC_EINVAL;
     double imn[4] = {0, 0, 0, 0};
     if (t->P.images) orc_kelvin(t->P.a, t->gamma, rn[0], rn[1], rn[2], t->q[i], imn);
@@ -836,10 +952,14 @@ int orc_tree_commit(otree *t, int64_t i, const double *rn) {
  * phi_out (nullable) receives phi_{X_i}(r_i). */
 double orc_tree_energy(otree *t, double *phi_out) {
     nsum e = {0, 0};
-    int nex = t->P.images ? 2 : 1;
+    int M = t->P.images ? t->P.line_images : 0;
+    int nex = t->P.images ? 2 + M : 1;
     double a = t->P.a;
+    orc_lines L;
+    lines_of(&t->P, &L);
     for (int i = 0; i < t->n; ++i) {
-        int ex[2] = {i, t->n + i};
+        int ex[10] = {i, t->n + i};  /* the ion and all of its images */
+        for (int m = 0; m < M; ++m) ex[2 + m] = 2 * t->n + m * t->n + i;
         double r[3] = {t->x[i], t->y[i], t->z[i]};
         double phi = tree_phi(t, r, ex, nex, NULL);
         if (phi_out) phi_out[i] = phi;
@@ -847,6 +967,9 @@ double orc_tree_energy(otree *t, double *phi_out) {
         if (t->P.geom == 1) {
             double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             if (t->P.images) nadd(&e, 0.5 * t->gamma * a * t->q[i] * t->q[i] / (r2 - a * a));
+            /* own line images: -sigma w_m q_K at t_m r_K, |r - t_m r_K| = (r^2 - t_m a^2) / r */
+            for (int m = 0; m < L.M; ++m)
+                nadd(&e, -0.5 * L.sigma * L.w[m] * t->gamma * a * t->q[i] * t->q[i] / (r2 - L.t[m] * a * a));
             if (t->P.Q_center != 0.0) nadd(&e, t->P.Q_center * t->q[i] / sqrt(r2));
         }
     }
@@ -961,6 +1084,7 @@ static void grad_visit(const otree *t, int c, int tg, const int *ex, int nex, gs
 
 /* dE_tree/dr_i and dE_tree/dq_i for every ion; returns E_tree. */
 double orc_tree_grad(otree *t, double *gx, double *gy, double *gz, double *gq) {
+    if (t->P.line_images) return NAN;  /* the multiple-image model: energies only */
     int ns = t->nsrc, n = t->n, nex = t->P.images ? 2 : 1;
     gstate g;
     g.gx = (double *)calloc(ns, sizeof(double)); g.gy = (double *)calloc(ns, sizeof(double));
@@ -1032,6 +1156,7 @@ int orc_mc_run(otree **tp, uint64_t seed, uint32_t replica, uint64_t move0, int6
                double step, uint8_t *accept_bits, double *dE_out, int64_t *i_out,
                int64_t *stats) {
     memset(stats, 0, sizeof(int64_t) * 5);
+    if ((*tp)->P.line_images) return ORC_EINVAL;  /* the multiple-image model: energies only */
     int64_t rebuilt_at = -1;
     for (int64_t k = 0; k < n_moves; ++k) {
         otree *t = *tp;
@@ -1075,6 +1200,7 @@ int orc_direct_mc_run(const orc_params *P, int64_t n, double *x, double *y, doub
                       int64_t n_moves, double step, uint8_t *accept_bits, double *dE_out,
                       int64_t *stats) {
     memset(stats, 0, sizeof(int64_t) * 5);
+    if (P->line_images) return ORC_EINVAL;  /* the multiple-image model: energies only */
     double tau2 = P->hard_core * P->hard_core;
     for (int64_t k = 0; k < n_moves; ++k) {
         uint64_t m = move0 + (uint64_t)k;

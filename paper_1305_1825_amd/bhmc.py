@@ -29,7 +29,7 @@ class Params(C.Structure):
         ("box_lo", C.c_double * 3), ("box_side", C.c_double),
         ("a", C.c_double), ("Q_center", C.c_double), ("eps_in", C.c_double), ("eps_out", C.c_double),
         ("r_min", C.c_double), ("r_max", C.c_double), ("hard_core", C.c_double),
-        ("slot_slack", C.c_int32), ("far_fp32", C.c_int32),
+        ("slot_slack", C.c_int32), ("far_fp32", C.c_int32), ("line_images", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -119,8 +119,8 @@ def _check(st, what):
 def make_params(d: dict) -> Params:
     p = Params()
     for name, _ in Params._fields_:
-        if name == "far_fp32":
-            p.far_fp32 = int(d.get("far_fp32", 0))
+        if name in ("far_fp32", "line_images", "reserved"):
+            setattr(p, name, int(d.get(name, 0)))
             continue
         if name == "box_lo":
             p.box_lo[:] = [float(v) for v in d["box_lo"]]

@@ -183,6 +183,71 @@ static bhmc_status fail(bhmc_status st, const char* fmt, ...) {
 
 extern "C" const char* bhmc_last_error(void) { return g_err.c_str(); }
 
+// The M-point Gauss rule for the weight t^(sigma - 1) on [0, 1], the line image of the
+// multiple-image model: by Golub and Welsch, the nodes are the eigenvalues of the
+// symmetric tridiagonal Jacobi matrix of the polynomials orthogonal for that weight (the
+// Jacobi polynomials P^(0, sigma - 1) moved to [0, 1]) and the weights are the squared
+// first components of its unit eigenvectors times the weight's integral 1 / sigma.  The
+// eigenproblem (at most 8 x 8) is solved by cyclic Jacobi rotations.  Nodes descending,
+// nodes and weights rounded to multiples of 2^-40 (far below the rule's own error).
+static bool line_rule(double sigma, int M, double* t, double* w) {
+    if (M < 1 || M > 8 || !(sigma >= 0.5 && sigma <= 1.0)) return false;
+    const double b = sigma - 1.0;
+    double A[8][8] = {}, V[8][8] = {};
+    for (int k = 0; k < M; ++k) {
+        // recurrence coefficients of the monic Jacobi (0, b) polynomials on [-1, 1]
+        const double c = 2.0 * k + b;
+        const double diag = k == 0 ? b / (b + 2.0) : (b * b) / (c * (c + 2.0));
+        A[k][k] = 0.5 * (1.0 + diag);  // t = (1 + x) / 2
+        if (k + 1 < M) {
+            const double j = k + 1.0, c1 = 2.0 * j + b;
+            const double beta = 4.0 * j * j * (j + b) * (j + b) / (c1 * c1 * (c1 + 1.0) * (c1 - 1.0));
+            A[k][k + 1] = A[k + 1][k] = 0.5 * std::sqrt(beta);
+        }
+        V[k][k] = 1.0;
+    }
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < M; ++i) {
+            diag += A[i][i] * A[i][i];
+            for (int j = i + 1; j < M; ++j) off += A[i][j] * A[i][j];
+        }
+        if (off <= 1e-34 * diag) break;
+        for (int p = 0; p < M; ++p)
+            for (int q = p + 1; q < M; ++q) {
+                if (A[p][q] == 0.0) continue;
+                // the rotation in the (p, q) plane that zeroes A[p][q]
+                const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double tn = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(tn * tn + 1.0), sn = tn * cs;
+                for (int k = 0; k < M; ++k) {  // columns p and q
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = cs * akp - sn * akq;
+                    A[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < M; ++k) {  // rows p and q
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = cs * apk - sn * aqk;
+                    A[q][k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < M; ++k) {
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = cs * vkp - sn * vkq;
+                    V[k][q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    int order[8];
+    for (int k = 0; k < M; ++k) order[k] = k;
+    std::sort(order, order + M, [&](int i, int j) { return A[i][i] > A[j][j]; });
+    for (int m = 0; m < M; ++m) {
+        const int k = order[m];
+        t[m] = std::ldexp(std::nearbyint(std::ldexp(A[k][k], 40)), -40);
+        w[m] = std::ldexp(std::nearbyint(std::ldexp(V[0][k] * V[0][k] / sigma, 40)), -40);
+    }
+    return true;
+}
+
 static bhmc_status check_params(const bhmc_params& P, int64_t n) {
     if (n < 1 || n > (1 << 22)) return fail(BHMC_EINVAL, "n = %lld out of range [1, 2^22]", (long long)n);
     if (!(P.theta >= 0.0 && P.theta < 1.0)) return fail(BHMC_EINVAL, "theta must lie in [0, 1)");
@@ -205,6 +270,22 @@ static bhmc_status check_params(const bhmc_params& P, int64_t n) {
         return fail(BHMC_EINVAL, "images need 0 < a <= r_min and eps_in > 0");
     if (!(P.hard_core >= 0.0) || !(P.l_B >= 0.0)) return fail(BHMC_EINVAL, "hard_core and l_B must be >= 0");
     if (P.far_fp32 != 0 && P.far_fp32 != 1) return fail(BHMC_EINVAL, "far_fp32 must be 0 or 1");
+    if (P.line_images < 0 || P.line_images > 8) return fail(BHMC_EINVAL, "line_images must lie in [0, 8]");
+    if (P.line_images > 0) {
+        const double sigma = P.eps_out / (P.eps_in + P.eps_out);
+        if (!P.images) return fail(BHMC_EINVAL, "line images need images = 1");
+        if (P.n0 != 0) return fail(BHMC_EINVAL, "line images need N_0 = 0");
+        if (!(sigma >= 0.5 && sigma <= 1.0)) return fail(BHMC_EINVAL, "line images need eps_in <= eps_out");
+        if ((2 + P.line_images) * n > (1 << 23)) return fail(BHMC_EINVAL, "too many sources with line images");
+    }
+    return BHMC_OK;
+}
+
+// The multiple-image model is evaluated by bhmc_energy (and bhmc_energy_noalloc) only.
+static bhmc_status energy_only(const bhmc_tree* t, const char* what) {
+    for (const bhmc_params& P : t->params)
+        if (P.line_images > 0)
+            return fail(BHMC_EINVAL, "%s: the multiple-image model (line_images > 0) supports bhmc_energy only", what);
     return BHMC_OK;
 }
 
@@ -230,7 +311,16 @@ static void fill_rep(Rep& r, const bhmc_params& P, int64_t n) {
     r.far32 = P.far_fp32 ? 1 : 0;
     r.max_depth = P.max_depth; r.slack = P.slot_slack;
     r.n = (int)n;
-    r.nsrc = P.images ? 2 * (int)n : (int)n;
+    r.nline = 0;
+    if (P.images && P.line_images > 0) {
+        const double sigma = P.eps_out / (P.eps_in + P.eps_out);
+        double w[8];
+        if (line_rule(sigma, P.line_images, r.line_t, w)) {
+            r.nline = P.line_images;
+            for (int m = 0; m < r.nline; ++m) r.line_c[m] = -sigma * w[m];
+        }
+    }
+    r.nsrc = P.images ? (2 + r.nline) * (int)n : (int)n;
     r.fcap = 4096;
 }
 
@@ -610,7 +700,7 @@ extern "C" bhmc_status bhmc_energy(bhmc_tree* t, int32_t replica, double* E_host
     const int n = t->host[replica].n;
     if ((st = ensure_eterm(t, n))) return st;
     for (;;) {
-        t->ops->energy(t->stream, t->reps, replica, n, phi_dev, t->eterm, energy_grid_bound(t));
+        t->ops->energy(t->stream, t->reps, replica, n, phi_dev, t->eterm, energy_grid_bound(t), t->host[replica].nline);
         HIP_TRY(hipGetLastError());
         bool again = false;
         if ((st = finish_energy(t, replica, n, E_host, "energy", &again)) || !again) return st;
@@ -629,7 +719,7 @@ extern "C" bhmc_status bhmc_energy_noalloc(bhmc_tree* t, int32_t replica, double
         return fail(BHMC_EINVAL, "replica %d has %d ions; the allocation-free energy takes at most %d", replica, n,
                     kScratchDoubles);
     if (!t->scratch) return fail(BHMC_EHIP, "scratch array not resolved");
-    t->ops->energy(t->stream, t->reps, replica, n, phi_dev, t->scratch, energy_grid_bound(t));
+    t->ops->energy(t->stream, t->reps, replica, n, phi_dev, t->scratch, energy_grid_bound(t), t->host[replica].nline);
     bhmc::launch_sum(t->stream, t->scratch, n, t->host[replica].l_B, E_dev);
     HIP_TRY(hipGetLastError());
     return BHMC_OK;
@@ -640,7 +730,7 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* dEdr_dev, double* dEdq_dev,
                                         double* E_host) {
     bhmc_status st = check_rep(t, replica);
-    if (st) return st;
+    if (st || (st = energy_only(t, "bhmc_energy_grad"))) return st;
     if (!dEdr_dev || !dEdq_dev) return fail(BHMC_EINVAL, "null gradient output");
     if (!t->ops->grad) return fail(BHMC_EINVAL, "gradient not available for p = %d", t->p);
     const Rep& h = t->host[replica];
@@ -713,7 +803,10 @@ static bhmc_status run_move(bhmc_tree* t, int64_t i, const double* r_new, int mo
 extern "C" bhmc_status bhmc_delta_energy(bhmc_tree* tree, int64_t i, const double* r_new, double* dE_host,
                                          int32_t* reason_host) {
     bhmc::MoveIO io;
-    bhmc_status st = run_move(tree, i, r_new, 0, io);
+    if (!tree) return fail(BHMC_EINVAL, "null tree");
+    bhmc_status st = energy_only(tree, "bhmc_delta_energy");
+    if (st) return st;
+    st = run_move(tree, i, r_new, 0, io);
     if (st) return st;
     if (dE_host) *dE_host = io.reason ? HUGE_VAL : io.dE;
     if (reason_host) *reason_host = io.reason;
@@ -722,7 +815,10 @@ extern "C" bhmc_status bhmc_delta_energy(bhmc_tree* tree, int64_t i, const doubl
 
 extern "C" bhmc_status bhmc_commit_move(bhmc_tree* tree, int64_t i, const double* r_new) {
     bhmc::MoveIO io;
-    bhmc_status st = run_move(tree, i, r_new, 1, io);
+    if (!tree) return fail(BHMC_EINVAL, "null tree");
+    bhmc_status st = energy_only(tree, "bhmc_commit_move");
+    if (st) return st;
+    st = run_move(tree, i, r_new, 1, io);
     if (st) return st;
     if (io.reason == 1) return fail(BHMC_EINVAL, "the move leaves the confinement");
     if (io.reason == 2) return fail(BHMC_EOVERLAP, "the move overlaps a hard core");
@@ -791,7 +887,7 @@ static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArg
 extern "C" bhmc_status bhmc_mc_run(bhmc_tree* t, int32_t replica, uint64_t seed, uint64_t move0,
                                    int64_t n_moves, double step, uint8_t* accept_dev, bhmc_stats* stats_host) {
     bhmc_status st = check_rep(t, replica);
-    if (st) return st;
+    if (st || (st = energy_only(t, "bhmc_mc_run"))) return st;
     if (n_moves < 0 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad n_moves or step");
     if ((st = download(t))) return st;
     Rep& h = t->host[replica];
@@ -875,8 +971,8 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
                                         int32_t use_graph, bhmc_stats* stats_host) {
     if (!t) return fail(BHMC_EINVAL, "null tree");
     if (n_sweeps < 0 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad n_sweeps or step");
-    bhmc_status st = download(t);
-    if (st) return st;
+    bhmc_status st = energy_only(t, "bhmc_batch_sweep");
+    if (st || (st = download(t))) return st;
     for (int r = 0; r < t->R; ++r) {
         t->host[r].move_next = t->host[r].move_end;  // sweeps continue from the chain's end
         t->host[r].mc_status = 0;
@@ -941,8 +1037,8 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
                                            int32_t* choice, float* ms_out) {
     if (!t) return fail(BHMC_EINVAL, "null tree");
     if (trial_moves < 1 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad trial_moves or step");
-    bhmc_status st = download(t);
-    if (st) return st;
+    bhmc_status st = energy_only(t, "bhmc_batch_autotune");
+    if (st || (st = download(t))) return st;
     for (int r = 0; r < t->R; ++r)
         if (t->host[r].move_end != 0 || t->host[r].stats[0] != 0)
             return fail(BHMC_EINVAL, "autotune needs replicas as built (replica %d has moved)", r);

@@ -1,6 +1,6 @@
 // Tree construction kernels: one workgroup per replica.
 //
-//   k_sources   ions copied in, Kelvin images made, confinement checked, keys
+//   k_sources   ions copied in, Kelvin (and line) images made, confinement checked, keys
 //   k_sort      stable LSD radix sort of (key, source) in LDS-ranked tiles
 //   k_count     number of split cells per level, straight from sorted keys
 //   k_topology  cells level by level (Sec. 3.2 bisection, adaptive by count)
@@ -45,6 +45,15 @@ k_sources(Rep* reps, const int* rep_list, const double* x, const double* y, cons
             R.src[n + i] = im;
             R.keys[n + i] = morton_key(R, im.x, im.y, im.z);
             R.perm[n + i] = n + i;
+            // line images (multiple-image model): source 2n + m n + i at t_m r_K, charge c_m q_K
+            for (int m = 0; m < R.nline; ++m) {
+                const int s = 2 * n + m * n + i;
+                const double4 li = make_double4(R.line_t[m] * im.x, R.line_t[m] * im.y, R.line_t[m] * im.z,
+                                                R.line_c[m] * im.w);
+                R.src[s] = li;
+                R.keys[s] = morton_key(R, li.x, li.y, li.z);
+                R.perm[s] = s;
+            }
         }
     }
     if (my_bad) atomicOr(&bad, my_bad);

@@ -36,6 +36,10 @@ struct Rep {
     double hi[3];                  // lo + side per axis (cube walls)
     int geom, images, leaf_cap, n0, max_depth, slack;
     int far32;                     // far field from the single-precision moments (M32)
+    // multiple images: nline line-image points per ion, source 2n + m n + i at line_t[m] times
+    // the Kelvin point with line_c[m] times the Kelvin charge (energies only)
+    int nline;
+    double line_t[8], line_c[8];
     int n, nsrc;
     // ---- sizes (kernels)
     int ncell, nleaf, pool, depth, nsplit;

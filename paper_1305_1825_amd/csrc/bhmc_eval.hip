@@ -1982,10 +1982,55 @@ void run_mcb(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide) {
 void run_move(hipStream_t s, Rep* reps, int r, MoveIO* io) {
     hipLaunchKernelGGL(k_move, dim3(1), dim3(kMcBlock), 0, s, reps, r, io);
 }
-void run_energy(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm, int max_grid) {
+// Line images of the multiple-image model (one thread per ion, after k_energy): an
+// ion's own line images stay in its traversal as sources, so each is taken back out of
+// its potential and energy term where the traversal met it.  With N_0 = 0 the
+// traversal takes a source through the first cell of its root path that passes the MAC
+// (the expansion of eq. 3.3 of that one point source), else directly at its leaf.  The
+// ion's energy with its own line images, 1/2 q sum_m c_m q_K / |r - t_m r_K|, is added.
+__global__ void __launch_bounds__(256) k_eline(Rep* reps, int r, double* phi, double* eterm) {
+    const Rep& R = reps[r];
+    const int ion = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ion >= R.n) return;
+    const double4 si = R.src[ion];
+    double sub = 0.0;
+    for (int m = 0; m < R.nline; ++m) {
+        const double4 sc = R.src[2 * R.n + m * R.n + ion];
+        const uint64_t key = morton_key(R, sc.x, sc.y, sc.z);
+        double v = 0.0;
+        int c = 0;
+        for (int level = 0;; ++level) {
+            if (c < 0 || c >= R.ncell || level > kMaxDepth) { reps[r].err_detail = kErrPathCell; v = __builtin_nan(""); break; }
+            const double4 g = R.cgeo[c];
+            const double dx = g.x - si.x, dy = g.y - si.y, dz = g.z - si.z;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (3.0 * (g.w * g.w) <= R.theta2 * d2) {
+                v = point_expansion(dx, dy, dz, sc.x - g.x, sc.y - g.y, sc.z - g.z);
+                break;
+            }
+            const int link = R.cm[c].y;
+            if (link < 0) {
+                const double ex = si.x - sc.x, ey = si.y - sc.y, ez = si.z - sc.z;
+                v = rsqrt_nr(ex * ex + ey * ey + ez * ez);
+                break;
+            }
+            if (link + 8 > R.ncell) { reps[r].err_detail = kErrChildLink; v = __builtin_nan(""); break; }
+            c = link + key_digit(key, level + 1);
+        }
+        sub += sc.w * v;
+    }
+    const double r2 = si.x * si.x + si.y * si.y + si.z * si.z;
+    double self = 0.0;  // own line images: c_m q_K at t_m r_K, |r - t_m r_K| = (r^2 - t_m a^2) / r
+    for (int m = 0; m < R.nline; ++m) self += R.line_c[m] * R.gamma * R.a * si.w / (r2 - R.line_t[m] * R.a2);
+    if (phi) phi[ion] -= sub;
+    eterm[ion] += 0.5 * si.w * (self - sub);
+}
+
+void run_energy(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm, int max_grid, int nline) {
     int grid = (n + kEnergyTargets - 1) / kEnergyTargets;
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
     hipLaunchKernelGGL(k_energy, dim3(grid), dim3(kEnergyBlock), 0, s, reps, r, phi, eterm);
+    if (nline > 0) hipLaunchKernelGGL(k_eline, dim3((n + 255) / 256), dim3(256), 0, s, reps, r, phi, eterm);
 }
 void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq, double* eterm,
               int max_grid) {

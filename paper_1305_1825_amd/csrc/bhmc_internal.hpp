@@ -68,7 +68,8 @@ struct EvalOps {
     void (*move)(hipStream_t s, Rep* reps, int r, MoveIO* io_dev);
     // max_grid > 0 bounds the number of workgroups (each then takes several target groups), so that
     // every workgroup has an HBM frontier region
-    void (*energy)(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm, int max_grid);
+    // nline > 0: the replica has line images (multiple-image model), corrected after the traversal
+    void (*energy)(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm, int max_grid, int nline);
     void (*grad)(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, double* dEdq,
                  double* eterm, int max_grid);
     // phase timers of the batched Metropolis kernel: number of counters, 0 without timers

@@ -24,7 +24,7 @@ except Exception:  # pragma: no cover
 BASE_PARAMS = dict(
     l_B=1.0, theta=0.5, p=4, leaf_cap=8, n0=0, max_depth=21, geom=0, images=0,
     box_lo=(0.0, 0.0, 0.0), box_side=20.0, a=0.0, Q_center=0.0, eps_in=1.0, eps_out=1.0,
-    r_min=0.0, r_max=0.0, hard_core=0.0, slot_slack=2, far_fp32=0,
+    r_min=0.0, r_max=0.0, hard_core=0.0, slot_slack=2, far_fp32=0, line_images=0,
 )
 
 

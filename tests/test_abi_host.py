@@ -34,7 +34,13 @@ def test_library_exports_every_declared_symbol():
                                  dict(leaf_cap=(1 << 23) + 1),
                                  # shell configurations whose root cube misses part of the shell
                                  W.shell_params(10.0, 0.0, 10.5, 40.0, box_side=79.0),
-                                 W.shell_params(10.0, 0.0, 10.5, 40.0, box_lo=(-40.0, -39.0, -40.0))])
+                                 W.shell_params(10.0, 0.0, 10.5, 40.0, box_lo=(-40.0, -39.0, -40.0)),
+                                 # the multiple-image model: M in 0..8, images on, N_0 = 0, eps_in <= eps_out
+                                 dict(W.shell_params(10.0, 0.0, 10.5, 40.0), line_images=9),
+                                 dict(W.shell_params(10.0, 0.0, 10.5, 40.0), line_images=-1),
+                                 dict(W.shell_params(10.0, 0.0, 10.5, 40.0), line_images=2, images=0),
+                                 dict(W.shell_params(10.0, 0.0, 10.5, 40.0), line_images=2, n0=4),
+                                 dict(W.shell_params(10.0, 0.0, 10.5, 40.0), line_images=2, eps_in=80.0, eps_out=2.0)])
 def test_parameter_validation_on_host(bad):
     P = W.make_params(**bad)
     pp = bhmc.make_params(P)

@@ -1,0 +1,146 @@
+"""Pins of the oracle's multiple-image model of the dielectric sphere (the model the
+paper names in Sec. 1 and Sec. 5 without formulas).
+
+A unit charge at y outside a sphere of radius a (eps_in inside, eps_out outside)
+has the reaction potential sum_n b_n a^(2n+1) / (|y|^(n+1) |x|^(n+1)) P_n(cos angle)
+with b_n = n (eps_out - eps_in) / (n eps_in + (n + 1) eps_out): the textbook
+solution of Laplace's equation with continuous potential and normal displacement
+on the sphere.  The oracle represents it by the Kelvin image plus M points of a
+line image placed by a Gauss rule of the weight t^(sigma - 1) on [0, 1]; here the
+rule is pinned by its moments (and by Gauss-Legendre at sigma = 1), the image
+potential by the Legendre series itself, and the treecode energy with line images
+by the direct sum."""
+import numpy as np
+import pytest
+from scipy.special import eval_legendre
+
+import oracle as O
+from paper_1305_1825_amd import workloads as W
+
+A, EIN, EOUT = 10.0, 2.0, 80.0
+SIGMA = EOUT / (EIN + EOUT)
+
+
+def exact_reaction(x, y, nmax=3000):
+    """The Legendre series of the reaction potential at x of a unit charge at y."""
+    rx, ry = np.linalg.norm(x), np.linalg.norm(y)
+    c = np.clip(np.dot(x, y) / (rx * ry), -1.0, 1.0)
+    n = np.arange(nmax + 1)
+    b = n * (EOUT - EIN) / (n * EIN + (n + 1) * EOUT)
+    return float(np.sum(b * (A / (rx * ry)) * (A * A / (rx * ry)) ** n * eval_legendre(n, c)))
+
+
+def params(M, **kw):
+    P = W.shell_params(A, 0.0, 10.5, 40.0, theta=0.5, p=6, leaf_cap=8, hard_core=0.0)
+    return dict(P, eps_in=EIN, eps_out=EOUT, line_images=M, Q_center=0.0, **kw)
+
+
+def reaction_via_direct_phi(M, x, y):
+    """G_R(x; y) from the oracle's direct potential of a two-ion system."""
+    xs = np.array([x[0], y[0]]), np.array([x[1], y[1]]), np.array([x[2], y[2]])
+    phi = O.direct_phi(params(M), *xs, np.array([1.0, 1.0]))
+    return phi[0] - 1.0 / np.linalg.norm(np.asarray(x) - np.asarray(y))
+
+
+@pytest.mark.parametrize("sigma", [0.5, 0.75, SIGMA, 1.0])
+def test_line_rule_integrates_moments_exactly(sigma):
+    for M in range(1, 9):
+        t, w = O.line_rule(sigma, M)
+        assert np.all(np.diff(t) < 0) and np.all((t > 0) & (t < 1)) and np.all(w > 0)
+        for k in range(2 * M):
+            assert abs(np.sum(w * t ** k) - 1.0 / (k + sigma)) <= 5e-11, (sigma, M, k)  # rounding to 2^-40
+        # an M-point rule is not exact one degree further (the smallest such error here is 3.5e-10)
+        assert abs(np.sum(w * t ** (2 * M)) - 1.0 / (2 * M + sigma)) > 1e-10
+
+
+def test_line_rule_is_gauss_legendre_at_sigma_one():
+    for M in (1, 3, 8):
+        x, wl = np.polynomial.legendre.leggauss(M)
+        t, w = O.line_rule(1.0, M)
+        assert np.allclose(np.sort(t), (1.0 + x) / 2.0, atol=2e-12, rtol=0)
+        assert np.allclose(w[np.argsort(t)], wl / 2.0, atol=2e-12, rtol=0)
+
+
+PAIRS = [((12.0, 0.0, 0.0), (0.0, 13.0, 0.5)),
+         ((20.0, 5.0, 1.0), (-15.0, 3.0, 2.0)),
+         ((14.0, -3.0, 2.0), (11.0, 4.0, -6.0))]
+
+
+@pytest.mark.parametrize("pair", range(len(PAIRS)))
+def test_image_potential_converges_to_the_series(pair):
+    x, y = (np.array(v) for v in PAIRS[pair])
+    ex = exact_reaction(x, y)
+    errs = [abs(reaction_via_direct_phi(M, x, y) - ex) / abs(ex) for M in (1, 2, 4, 8)]
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] <= 1e-9, errs
+    # the Kelvin image alone keeps a net image charge (its b_0 is gamma, not 0)
+    kelvin = reaction_via_direct_phi(0, x, y)
+    assert abs(kelvin - ex) / abs(ex) > 1e-2
+
+
+def test_image_potential_near_the_sphere():
+    x, y = np.array([10.6, 0.2, 0.0]), np.array([10.7, 0.0, 0.3])
+    ex = exact_reaction(x, y, nmax=20000)
+    assert abs(reaction_via_direct_phi(8, x, y) - ex) / abs(ex) <= 1e-5
+
+
+def test_image_kernel_is_symmetric():
+    for x, y in PAIRS:
+        assert abs(reaction_via_direct_phi(6, x, y) - reaction_via_direct_phi(6, y, x)) <= 1e-15
+
+
+def test_self_energy_matches_the_series():
+    for r, tol in ((10.8, 1e-5), (13.0, 1e-8), (25.0, 1e-10)):  # down to the 2^-40 rounding of the rule
+        x = np.array([r / np.sqrt(3.0)] * 3)
+        ex = 0.5 * exact_reaction(x, x, nmax=20000)
+        errs = []
+        for M in (2, 4, 8):
+            E = O.direct_energy(dict(params(M), l_B=1.0), *(np.array([v]) for v in x), np.array([1.0]))
+            errs.append(abs(E - ex) / abs(ex))
+        assert errs[0] > errs[1] > errs[2] or errs[2] <= 1e-13, (r, errs)
+        assert errs[2] <= tol, (r, errs)
+
+
+def test_image_charges_of_an_ion_sum_to_zero_and_lie_on_the_ray():
+    c = W.config_colloid_10k(n=300, p=4)
+    P = dict(c["params"], line_images=5)
+    t = O.Tree(P, c["x"], c["y"], c["z"], c["q"])
+    xs, ys, zs, qs = t.sources()
+    n = len(c["x"])
+    assert len(xs) == 7 * n
+    tt, ww = O.line_rule(P["eps_out"] / (P["eps_in"] + P["eps_out"]), 5)
+    for i in (0, 17, n - 1):
+        imgs = [n + i] + [2 * n + m * n + i for m in range(5)]
+        qk = qs[n + i]
+        assert abs(sum(qs[s] for s in imgs)) <= 2e-11 * abs(qk)
+        for m in range(5):
+            s = 2 * n + m * n + i
+            assert np.allclose([xs[s], ys[s], zs[s]], tt[m] * np.array([xs[n + i], ys[n + i], zs[n + i]]),
+                               rtol=0, atol=1e-15)
+
+
+def test_tree_energy_with_line_images_equals_direct_at_theta0_and_converges():
+    c = W.config_colloid_10k(n=400, p=4)
+    P = dict(c["params"], line_images=4)
+    x, y, z, q = c["x"], c["y"], c["z"], c["q"]
+    Ed = O.direct_energy(P, x, y, z, q)
+    E0 = O.Tree(dict(P, theta=0.0), x, y, z, q).energy()
+    assert abs(E0 - Ed) <= 1e-11 * abs(Ed) + 1e-12
+    # at theta = 0.5 the treecode error falls with p
+    errs = [abs(O.Tree(dict(P, theta=0.5, p=p), x, y, z, q).energy() - Ed) for p in (2, 6, 10)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] <= 1e-6 * abs(Ed)
+    # the model changes the energy: the Kelvin image alone gives another value
+    Ek = O.direct_energy(dict(P, line_images=0), x, y, z, q)
+    assert abs(Ek - Ed) > 1e-3 * abs(Ed)
+
+
+def test_oracle_line_images_energies_only():
+    c = W.config_colloid_10k(n=200, p=4)
+    P = dict(c["params"], line_images=2)
+    t = O.Tree(P, c["x"], c["y"], c["z"], c["q"])
+    dE, reason = t.delta(0, np.array([c["x"][0], c["y"][0], c["z"][0]]) + 0.1)
+    assert np.isnan(dE)
+    with pytest.raises(Exception):
+        O.Tree(dict(P, line_images=9), c["x"], c["y"], c["z"], c["q"])
+    with pytest.raises(Exception):
+        O.Tree(dict(P, eps_in=80.0, eps_out=2.0), c["x"], c["y"], c["z"], c["q"])
