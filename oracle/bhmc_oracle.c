@@ -27,7 +27,7 @@
  *   - the multiple-image model of the dielectric sphere (Sec. 1 and Sec. 5
  *     name it without formulas): besides the Kelvin image, a line image from
  *     the sphere's centre to the Kelvin point, discretised by a Gauss-Jacobi
- *     rule; energies only.
+ *     rule; energies and Monte Carlo moves (no gradient).
  *
  * Every floating-point expression whose outcome decides an integer (a key, a
  * MAC decision, a wall or overlap test, a Metropolis decision) is written left
@@ -59,8 +59,8 @@ typedef struct {
     double eps_in, eps_out;
     double r_min, r_max; /* shell confinement (Sec. 4, spherical cell model)  */
     double hard_core;    /* contact distance tau (eq. 2.1)                    */
-    int32_t slot_slack;  /* leaf slots = slack * max(count, leaf_cap) + 2    */
-    int32_t line_images; /* 0, or M line-image points per ion (energies only) */
+    int32_t slot_slack;  /* leaf slots = slack * max(count, leaf_cap) + 2 + M */
+    int32_t line_images; /* 0, or M line-image points per ion (no gradient)  */
 } orc_params;
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOUTSIDE = -2, ORC_ECAPACITY = -6 };
@@ -285,17 +285,36 @@ static void lines_of(const orc_params *P, orc_lines *L) {
         L->M = P->line_images;
 }
 
+/* the line part alone: - sigma gamma a sum_m w_m / sqrt(D_{t_m}) */
+static double line_kernel(const orc_params *P, const orc_lines *L, double xi, double yi, double zi,
+                          double xj, double yj, double zj) {
+    double a = P->a, a2 = a * a, g = gamma_of(P);
+    double ri2 = xi * xi + yi * yi + zi * zi;
+    double rj2 = xj * xj + yj * yj + zj * zj;
+    double dot = xi * xj + yi * yj + zi * zj;
+    double v = 0.0;
+    for (int m = 0; m < L->M; ++m) {
+        double tt = L->t[m];
+        v -= L->sigma * L->w[m] * g * a / sqrt(ri2 * rj2 - 2.0 * tt * a2 * dot + tt * tt * a2 * a2);
+    }
+    return v;
+}
+
 static double image_kernel(const orc_params *P, const orc_lines *L, double xi, double yi, double zi,
                            double xj, double yj, double zj) {
     double a = P->a, a2 = a * a, g = gamma_of(P);
     double ri2 = xi * xi + yi * yi + zi * zi;
     double rj2 = xj * xj + yj * yj + zj * zj;
     double dot = xi * xj + yi * yj + zi * zj;
-    double v = g * a / sqrt(ri2 * rj2 - 2.0 * a2 * dot + a2 * a2);
-    for (int m = 0; m < L->M; ++m) {
-        double tt = L->t[m];
-        v -= L->sigma * L->w[m] * g * a / sqrt(ri2 * rj2 - 2.0 * tt * a2 * dot + tt * tt * a2 * a2);
-    }
+    return g * a / sqrt(ri2 * rj2 - 2.0 * a2 * dot + a2 * a2) + line_kernel(P, L, xi, yi, zi, xj, yj, zj);
+}
+
+/* Self term of the line images of a charge q at squared radius r2:
+ * 1/2 q^2 sum_m (-sigma w_m gamma a) / (r2 - t_m a^2), since the line image at
+ * t_m r_K lies on the ion's own ray at distance (r2 - t_m a^2) / |r|. */
+static double line_self(const orc_params *P, const orc_lines *L, double q, double r2) {
+    double a = P->a, g = gamma_of(P), v = 0.0;
+    for (int m = 0; m < L->M; ++m) v += -0.5 * L->sigma * L->w[m] * g * a * q * q / (r2 - L->t[m] * a * a);
     return v;
 }
 
@@ -391,10 +410,11 @@ double orc_direct_energy(const orc_params *P, int64_t n, const double *x, const 
  * summed (Sec. 1: V_i evaluated at the old and the new position). */
 double orc_direct_delta(const orc_params *P, int64_t n, const double *x, const double *y,
                         const double *z, const double *q, int64_t i, const double *rn) {
-    if (P->line_images) return NAN;  /* the multiple-image model: energies only */
     nsum e = {0, 0};
     int shell = P->geom == 1;
     double g = gamma_of(P), a = P->a;
+    orc_lines L;
+    lines_of(P, &L);
     double xo = x[i], yo = y[i], zo = z[i];
     for (int64_t j = 0; j < n; ++j) {
         if (j == i) continue;
@@ -405,6 +425,9 @@ double orc_direct_delta(const orc_params *P, int64_t n, const double *x, const d
             double Dn = img_D(a, rn[0], rn[1], rn[2], x[j], y[j], z[j]);
             double Do = img_D(a, xo, yo, zo, x[j], y[j], z[j]);
             t += g * a * q[j] * (1.0 / sqrt(Dn) - 1.0 / sqrt(Do));
+            if (L.M)
+                t += q[j] * (line_kernel(P, &L, rn[0], rn[1], rn[2], x[j], y[j], z[j]) -
+                             line_kernel(P, &L, xo, yo, zo, x[j], y[j], z[j]));
         }
         nadd(&e, q[i] * t);
     }
@@ -412,6 +435,7 @@ double orc_direct_delta(const orc_params *P, int64_t n, const double *x, const d
         double rn2 = rn[0] * rn[0] + rn[1] * rn[1] + rn[2] * rn[2];
         double ro2 = xo * xo + yo * yo + zo * zo;
         nadd(&e, 0.5 * g * a * q[i] * q[i] * (1.0 / (rn2 - a * a) - 1.0 / (ro2 - a * a)));
+        if (L.M) nadd(&e, line_self(P, &L, q[i], rn2) - line_self(P, &L, q[i], ro2));
     }
     if (shell && P->Q_center != 0.0) {
         double rn1 = sqrt(rn[0] * rn[0] + rn[1] * rn[1] + rn[2] * rn[2]);
@@ -445,7 +469,7 @@ void orc_direct_phi(const orc_params *P, int64_t n, const double *x, const doubl
 void orc_direct_grad(const orc_params *P, int64_t n, const double *x, const double *y,
                      const double *z, const double *q, double *gx, double *gy, double *gz,
                      double *gq) {
-    if (P->line_images) return;  /* the multiple-image model: energies only */
+    if (P->line_images) return;  /* the multiple-image model has no gradient here */
     int shell = P->geom == 1, imgs = shell && P->images;
     double g = gamma_of(P), a = P->a, a2 = a * a;
     for (int64_t i = 0; i < n; ++i) {
@@ -591,7 +615,8 @@ static int build_cell(otree *t, int level, uint32_t ix, uint32_t iy, uint32_t iz
         int base = cnt > P->leaf_cap ? cnt : P->leaf_cap;
         L->cell = c;
         L->count = cnt;
-        L->cap = P->slot_slack * base + 2;  /* + 2: one move inserts at most two sources */
+        /* one move inserts at most the ion and its images: 2 + M sources */
+        L->cap = P->slot_slack * base + 2 + P->line_images;
         L->slot = (int *)malloc(sizeof(int) * (L->cap > 0 ? L->cap : 1));
         for (int k = 0; k < cnt; ++k) {
             int s = t->perm[begin + k];
@@ -841,17 +866,18 @@ static int overlaps(const otree *t, int64_t i, const double *rn) {
 
 /* Energy change of moving ion i to rn on the committed tree:
  *   l_B q_i [phi_X(rn) - phi_X(r_i)] + exact self-image change + exact
- *   central-charge change, X = {i, image of i}.
+ *   central-charge change, X = {i and all of its images}.
  * A move that leaves the cell (Sec. 4) or overlaps a hard core (eq. 2.1)
  * has dE = +inf and a reason code. */
 double orc_tree_delta(otree *t, int64_t i, const double *rn, int *reason, int64_t *counts) {
     *reason = REASON_NONE;
-    if (t->P.line_images) return NAN;  /* the multiple-image model: energies only */
     memset(&t->cnt, 0, sizeof(t->cnt));
     if (outside(&t->P, rn[0], rn[1], rn[2])) { *reason = REASON_WALL; return INFINITY; }
     if (overlaps(t, i, rn)) { *reason = REASON_OVERLAP; return INFINITY; }
-    int ex[2] = {(int)i, t->n + (int)i};
-    int nex = t->P.images ? 2 : 1;
+    int M = t->P.images ? t->P.line_images : 0;
+    int ex[10] = {(int)i, t->n + (int)i};
+    for (int m = 0; m < M; ++m) ex[2 + m] = 2 * t->n + m * t->n + (int)i;
+    int nex = t->P.images ? 2 + M : 1;
     double ro[3] = {t->x[i], t->y[i], t->z[i]};
     int coin = 0;
     double pn = tree_phi(t, rn, ex, nex, &coin);
@@ -865,6 +891,11 @@ double orc_tree_delta(otree *t, int64_t i, const double *rn, int *reason, int64_
         double ro2 = ro[0] * ro[0] + ro[1] * ro[1] + ro[2] * ro[2];
         if (t->P.images)
             dE += 0.5 * l * t->gamma * a * qi * qi * (1.0 / (rn2 - a * a) - 1.0 / (ro2 - a * a));
+        if (M) {
+            orc_lines L;
+            lines_of(&t->P, &L);
+            dE += l * (line_self(&t->P, &L, qi, rn2) - line_self(&t->P, &L, qi, ro2));
+        }
         if (t->P.Q_center != 0.0)
             dE += l * t->P.Q_center * qi * (1.0 / sqrt(rn2) - 1.0 / sqrt(ro2));
     }
@@ -879,18 +910,27 @@ static int leaf_for(const otree *t, uint64_t key) {
     return t->cell[c].leaf;
 }
 
-/* Would the add operations of this move overflow a leaf's index array?
- * The ion is moved first, then its image; counts are followed through. */
-static int capacity_ok(const otree *t, int64_t i, const double *rn, const double *imn) {
-    int lio = t->leaf_of[i], lin = leaf_for(t, key_of(&t->P, rn[0], rn[1], rn[2]));
-    if (lin != lio && t->leaf[lin].count + 1 > t->leaf[lin].cap) return 0;
-    if (!t->P.images) return 1;
-    int s = t->n + (int)i;
-    int lmo = t->leaf_of[s], lmn = leaf_for(t, key_of(&t->P, imn[0], imn[1], imn[2]));
-    if (lmn == lmo) return 1;
-    int c = t->leaf[lmn].count;
-    if (lin != lio) { if (lmn == lin) c += 1; if (lmn == lio) c -= 1; }
-    return c + 1 <= t->leaf[lmn].cap;
+/* Would the add operations of this move overflow a leaf's index array?  The
+ * moved sources (the ion, then its images in source order) are placed one after
+ * another, so each one's new leaf is checked with the counts the earlier ones
+ * leave behind. */
+static int capacity_ok(const otree *t, int ns, const int *src, const double (*pos)[4]) {
+    int leaf_o[10], leaf_n[10];
+    for (int k = 0; k < ns; ++k) {
+        leaf_o[k] = t->leaf_of[src[k]];
+        leaf_n[k] = leaf_for(t, key_of(&t->P, pos[k][0], pos[k][1], pos[k][2]));
+    }
+    for (int k = 0; k < ns; ++k) {
+        if (leaf_n[k] == leaf_o[k]) continue;
+        int c = t->leaf[leaf_n[k]].count;
+        for (int e = 0; e < k; ++e) {
+            if (leaf_n[e] == leaf_o[e]) continue;
+            if (leaf_n[e] == leaf_n[k]) c += 1;
+            if (leaf_o[e] == leaf_n[k]) c -= 1;
+        }
+        if (c + 1 > t->leaf[leaf_n[k]].cap) return 0;
+    }
+    return 1;
 }
 
 /* Local modification of one source (Sec. 3.3, Fig. 3): if it changes leaf,
@@ -932,16 +972,32 @@ static void move_source(otree *t, int s, double xn, double yn, double zn, double
     t->x[s] = xn; t->y[s] = yn; t->z[s] = zn; t->q[s] = qn;
 }
 
-/* Commit an accepted move of ion i to rn: the ion, then its image. */
+/* Commit an accepted move of ion i to rn: the ion, then its Kelvin image, then
+ * its line images m = 0 .. M-1 (placed as the build places them). */
 int orc_tree_commit(otree *t, int64_t i, const double *rn) {
-    if (i < 0 || i >= t->n || t->P.line_images) return ORC_EINVAL;
+    if (i < 0 || i >= t->n) return ORC_EINVAL;
     if (outside(&t->P, rn[0], rn[1], rn[2])) return ORC_EINVAL;
-    double imn[4] = {0, 0, 0, 0};
-    if (t->P.images) orc_kelvin(t->P.a, t->gamma, rn[0], rn[1], rn[2], t->q[i], imn);
-    if (!capacity_ok(t, i, rn, imn)) return ORC_ECAPACITY;
+    int src[10], ns = 1;
+    double pos[10][4];
+    src[0] = (int)i;
+    pos[0][0] = rn[0]; pos[0][1] = rn[1]; pos[0][2] = rn[2]; pos[0][3] = t->q[i];
+    if (t->P.images) {
+        double imn[4];
+        orc_kelvin(t->P.a, t->gamma, rn[0], rn[1], rn[2], t->q[i], imn);
+        src[1] = t->n + (int)i;
+        for (int k = 0; k < 4; ++k) pos[1][k] = imn[k];
+        ns = 2;
+        orc_lines L;
+        lines_of(&t->P, &L);
+        for (int m = 0; m < L.M; ++m, ++ns) {
+            src[ns] = 2 * t->n + m * t->n + (int)i;
+            pos[ns][0] = L.t[m] * imn[0]; pos[ns][1] = L.t[m] * imn[1]; pos[ns][2] = L.t[m] * imn[2];
+            pos[ns][3] = -L.sigma * L.w[m] * imn[3];
+        }
+    }
+    if (!capacity_ok(t, ns, src, (const double (*)[4])pos)) return ORC_ECAPACITY;
     double *mono = (double *)malloc(sizeof(double) * t->nterms);
-    move_source(t, (int)i, rn[0], rn[1], rn[2], t->q[i], mono);
-    if (t->P.images) move_source(t, t->n + (int)i, imn[0], imn[1], imn[2], imn[3], mono);
+    for (int k = 0; k < ns; ++k) move_source(t, src[k], pos[k][0], pos[k][1], pos[k][2], pos[k][3], mono);
     free(mono);
     return ORC_OK;
 }
@@ -1084,7 +1140,7 @@ static void grad_visit(const otree *t, int c, int tg, const int *ex, int nex, gs
 
 /* dE_tree/dr_i and dE_tree/dq_i for every ion; returns E_tree. */
 double orc_tree_grad(otree *t, double *gx, double *gy, double *gz, double *gq) {
-    if (t->P.line_images) return NAN;  /* the multiple-image model: energies only */
+    if (t->P.line_images) return NAN;  /* the multiple-image model has no gradient here */
     int ns = t->nsrc, n = t->n, nex = t->P.images ? 2 : 1;
     gstate g;
     g.gx = (double *)calloc(ns, sizeof(double)); g.gy = (double *)calloc(ns, sizeof(double));
@@ -1156,7 +1212,6 @@ int orc_mc_run(otree **tp, uint64_t seed, uint32_t replica, uint64_t move0, int6
                double step, uint8_t *accept_bits, double *dE_out, int64_t *i_out,
                int64_t *stats) {
     memset(stats, 0, sizeof(int64_t) * 5);
-    if ((*tp)->P.line_images) return ORC_EINVAL;  /* the multiple-image model: energies only */
     int64_t rebuilt_at = -1;
     for (int64_t k = 0; k < n_moves; ++k) {
         otree *t = *tp;
@@ -1173,7 +1228,7 @@ int orc_mc_run(otree **tp, uint64_t seed, uint32_t replica, uint64_t move0, int6
         if (acc) {
             int st = orc_tree_commit(t, i, rn);
             if (st == ORC_ECAPACITY) {
-                if (rebuilt_at == k) return ORC_ECAPACITY; /* cannot happen: caps hold 2 spare */
+                if (rebuilt_at == k) return ORC_ECAPACITY; /* cannot happen: caps hold 2 + M spare */
                 rebuilt_at = k;
                 st = rebuild(tp);
                 if (st) return st;
@@ -1200,7 +1255,6 @@ int orc_direct_mc_run(const orc_params *P, int64_t n, double *x, double *y, doub
                       int64_t n_moves, double step, uint8_t *accept_bits, double *dE_out,
                       int64_t *stats) {
     memset(stats, 0, sizeof(int64_t) * 5);
-    if (P->line_images) return ORC_EINVAL;  /* the multiple-image model: energies only */
     double tau2 = P->hard_core * P->hard_core;
     for (int64_t k = 0; k < n_moves; ++k) {
         uint64_t m = move0 + (uint64_t)k;

@@ -8,8 +8,9 @@ solution of Laplace's equation with continuous potential and normal displacement
 on the sphere.  The oracle represents it by the Kelvin image plus M points of a
 line image placed by a Gauss rule of the weight t^(sigma - 1) on [0, 1]; here the
 rule is pinned by its moments (and by Gauss-Legendre at sigma = 1), the image
-potential by the Legendre series itself, and the treecode energy with line images
-by the direct sum."""
+potential by the Legendre series itself, the treecode energy with line images by
+the direct sum, and a Monte Carlo move (which moves the ion, its Kelvin image and
+its line images) by the difference of direct energies and the direct-sum chain."""
 import numpy as np
 import pytest
 from scipy.special import eval_legendre
@@ -134,12 +135,85 @@ def test_tree_energy_with_line_images_equals_direct_at_theta0_and_converges():
     assert abs(Ek - Ed) > 1e-3 * abs(Ed)
 
 
-def test_oracle_line_images_energies_only():
+def own_sources(n, i, M):
+    return [i, n + i] + [2 * n + m * n + i for m in range(M)]
+
+
+@pytest.mark.parametrize("M", [1, 4, 8])
+def test_move_energy_change_is_the_difference_of_energies(M):
+    """The treecode energy change at theta = 0 and the direct one both equal the
+    difference of the direct energies before and after the move."""
+    c = W.config_colloid_10k(n=250, p=3)
+    P = dict(c["params"], line_images=M)
+    x, y, z, q = (np.array(c[k]) for k in "xyzq")
+    t = O.Tree(dict(P, theta=0.0), x, y, z, q)
+    E0 = O.direct_energy(P, x, y, z, q)
+    for i, shift in ((0, 0.7), (13, -1.1), (77, 2.5)):
+        rn = np.array([x[i], y[i], z[i]]) * (1.0 + 0.02 * shift) + shift
+        dEt, reason = t.delta(i, rn)
+        assert reason == 0
+        dEd = O.direct_delta(P, x, y, z, q, i, rn)
+        x2, y2, z2 = x.copy(), y.copy(), z.copy()
+        x2[i], y2[i], z2[i] = rn
+        dEE = O.direct_energy(P, x2, y2, z2, q) - E0
+        scale = abs(E0) + 1.0
+        assert abs(dEt - dEE) <= 1e-12 * scale and abs(dEd - dEE) <= 1e-12 * scale, (i, dEt, dEd, dEE)
+        # the line images change the move's energy: the Kelvin image alone gives another value
+        dEk = O.direct_delta(dict(P, line_images=0), x, y, z, q, i, rn)
+        assert abs(dEk - dEE) > 1e-6 * scale
+
+
+def test_leaves_keep_room_for_every_image_of_a_moved_ion():
+    c = W.config_colloid_10k(n=400, p=3)
+    for M in (0, 3, 8):
+        P = dict(c["params"], line_images=M, slot_slack=1, leaf_cap=4)
+        t = O.Tree(P, c["x"], c["y"], c["z"], c["q"])
+        lv = t.leaves()
+        count = lv["end"] - lv["begin"]
+        assert np.array_equal(lv["cap"], np.maximum(count, 4) + 2 + M)
+
+
+@pytest.mark.parametrize("max_depth", [3, 21])
+def test_tree_chain_with_line_images_is_the_direct_chain(max_depth):
+    """At theta = 0 the treecode chain (commits of the ion, its Kelvin image and its
+    line images; rebuilds when a leaf fills) is the direct-sum chain move for move,
+    and the tree it leaves equals a fresh build from its positions."""
+    c = W.config_colloid_10k(n=500, p=4)
+    P = dict(c["params"], line_images=3, leaf_cap=4, slot_slack=1, max_depth=max_depth, theta=0.0)
+    x, y, z, q = (np.array(c[k]) for k in "xyzq")
+    t = O.Tree(P, x, y, z, q)
+    moves = 2500
+    rt = t.mc_run(4, 0, 0, moves, 3.0)
+    rd = O.direct_mc_run(P, x, y, z, q, 4, 0, 0, moves, 3.0)
+    assert np.array_equal(rt["accept"], rd["accept"])
+    fin = np.isfinite(rd["dE"])
+    assert np.array_equal(fin, np.isfinite(rt["dE"]))
+    assert np.max(np.abs(rt["dE"][fin] - rd["dE"][fin])) <= 1e-12
+    assert np.array_equal(rt["stats"][[0, 1, 2, 4]], rd["stats"][[0, 1, 2, 4]])
+    if max_depth == 3:
+        assert rt["stats"][3] > 0  # the capacity check and rebuild ran
+    n = len(x)
+    xs, ys, zs, qs = t.sources()
+    assert np.array_equal(xs[:n], rd["x"]) and np.array_equal(ys[:n], rd["y"]) and np.array_equal(zs[:n], rd["z"])
+    f = O.Tree(P, rd["x"], rd["y"], rd["z"], q)
+    for a, b in zip(f.sources(), (xs, ys, zs, qs)):
+        assert np.array_equal(a, b)  # the moved line images sit where a build puts them
+    # moments repaired move by move equal the fresh moments of the same tree
+    Mi, Mf = t.cells()["M"], t.fresh_moments()
+    assert np.max(np.abs(Mi - Mf)) <= 1e-10 * np.max(np.abs(Mf))
+    assert abs(t.energy() - f.energy()) <= 1e-11 * abs(f.energy())
+    # every source sits in exactly one leaf slot, where its tracking says
+    lv = t.leaves()
+    seen = np.concatenate([t.leaf_slots(l) for l in range(len(lv["cell"]))])
+    assert np.array_equal(np.sort(seen), np.arange(len(xs)))
+
+
+def test_oracle_line_images_have_no_gradient():
     c = W.config_colloid_10k(n=200, p=4)
     P = dict(c["params"], line_images=2)
     t = O.Tree(P, c["x"], c["y"], c["z"], c["q"])
-    dE, reason = t.delta(0, np.array([c["x"][0], c["y"][0], c["z"][0]]) + 0.1)
-    assert np.isnan(dE)
+    E, _, _ = t.grad()
+    assert np.isnan(E)
     with pytest.raises(Exception):
         O.Tree(dict(P, line_images=9), c["x"], c["y"], c["z"], c["q"])
     with pytest.raises(Exception):
