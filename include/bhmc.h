@@ -76,7 +76,8 @@ enum { BHMC_REASON_NONE = 0, BHMC_REASON_WALL = 1, BHMC_REASON_OVERLAP = 2 };
  *              (distance <= tau) is rejected (eq. 2.1).  0 = point charges
  *              (a move onto another ion is then rejected as an overlap).
  *   slot_slack capacity of a leaf's index array is
- *              slot_slack * max(count at build, leaf_cap) + 2.
+ *              slot_slack * max(count at build, leaf_cap) + 2 + line_images
+ *              (one move inserts at most the ion and its images).
  *   far_fp32   1: the expansions of eq. 3.3 in the traversals of the energy,
  *              the energy change and the Metropolis kernels use a single-
  *              precision copy of the moments and single-precision Taylor
@@ -96,9 +97,11 @@ enum { BHMC_REASON_NONE = 0, BHMC_REASON_WALL = 1, BHMC_REASON_OVERLAP = 2 };
  *              eps_out / (eps_in + eps_out)); the line is replaced by the M-point
  *              Gauss rule of the weight t^(sigma-1) on [0, 1] (nodes t_m and
  *              weights w_m rounded to multiples of 2^-40): M more sources per
- *              ion, -sigma w_m q_K at t_m r_K, numbered 2n + m n + i.  Only
- *              bhmc_energy and bhmc_energy_noalloc evaluate it; the Monte Carlo,
- *              energy change, commit and gradient calls return BHMC_EINVAL.
+ *              ion, -sigma w_m q_K at t_m r_K, numbered 2n + m n + i.  The
+ *              energy, energy change, commit and Monte Carlo calls evaluate it
+ *              (a move then moves the ion, its Kelvin image and its M line
+ *              images, in that order; the Metropolis calls take one move per
+ *              traversal); bhmc_energy_grad returns BHMC_EINVAL.
  *   reserved   0.
  */
 typedef struct {
@@ -194,15 +197,16 @@ bhmc_status bhmc_energy_noalloc(bhmc_tree* tree, int32_t replica, double* E_dev,
  * the committed tree (Sec. 1: the particle's energy evaluated twice):
  *   dE = l_B q_i [phi(r_new) - phi(r_i)] + exact self-image change
  *        + exact central-charge change,
- * phi from every source except ion i and its image.  A move out of the
- * confinement or onto a hard core gives dE = +inf and *reason_host =
- * BHMC_REASON_WALL / BHMC_REASON_OVERLAP (not an error).  The tree is not
- * modified. */
+ * phi from every source except ion i and its images (the self-image change
+ * includes ion i's own line images).  A move out of the confinement or onto
+ * a hard core gives dE = +inf and *reason_host = BHMC_REASON_WALL /
+ * BHMC_REASON_OVERLAP (not an error).  The tree is not modified. */
 bhmc_status bhmc_delta_energy(bhmc_tree* tree, int64_t i, const double* r_new, double* dE_host,
                               int32_t* reason_host);
 
 /* Commit the move of ion i of replica 0 to r_new (host, 3 values) by the
- * local adjustment of Sec. 3.3: ion then image are moved between leaf index
+ * local adjustment of Sec. 3.3: ion then image (then the line images, in
+ * source order) are moved between leaf index
  * arrays (delete = last entry fills the hole; add = append) and their old and
  * new contributions are removed from / added to the moments and counts of
  * every ancestor cell.  EINVAL if the move leaves the confinement,
@@ -245,7 +249,7 @@ bhmc_status bhmc_batch_sweep(bhmc_tree* tree, uint64_t seed, int32_t n_sweeps, d
  * 256-thread workgroups, one per CU; 2: 256-thread workgroups, two per CU;
  * tile 0: one trial move per traversal (two targets); 1: half the most moves
  * per round the order allows; 2: the most (see bhmc_set_moves_per_round;
- * tiles 1 and 2 only when every replica has N_0 = 0, and tile 1 only when it
+ * tiles 1 and 2 only when every replica has N_0 = 0 and no line images, and tile 1 only when it
  * is above one move).  Every replica is rebuilt from its built positions
  * after each trial, and the fastest candidate is kept for the handle's later
  * bhmc_mc_run and bhmc_batch_sweep calls (replacing the moves per round set
@@ -291,9 +295,9 @@ bhmc_status bhmc_energy_grad(bhmc_tree* tree, int32_t replica, double* dEdr_dev,
  * traversal's decisions depend only on geometry and occupancy, so an accepted
  * move changes a later move's potentials only through its own contributions).
  * The chain -- accept stream, positions, statistics -- is the same as with one
- * move at a time, up to the rounding of the energy sums.  Replicas with N_0 > 0
- * always run one move at a time.  effective (nullable, host) receives the
- * moves per round the handle will use. */
+ * move at a time, up to the rounding of the energy sums.  Handles with a replica
+ * with N_0 > 0 or with line images always run one move at a time.  effective
+ * (nullable, host) receives the moves per round the handle will use. */
 bhmc_status bhmc_set_moves_per_round(bhmc_tree* tree, int32_t moves, int32_t* effective);
 
 /* Phase timers of the batched Metropolis kernel, present only in a library

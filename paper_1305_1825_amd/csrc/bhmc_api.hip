@@ -151,7 +151,7 @@ struct bhmc_tree {
     int allow_spill = 1;
     bool energy_bounded = false;     // energy / gradient launches keep their grid within the regions
     int moves_per_round = 0;         // 0: as many as the order allows; 1: the move-by-move kernel
-    bool all_n0_zero = true;         // the batched kernel needs N_0 = 0 on every replica
+    bool rounds_ok = true;           // the rounds kernel needs N_0 = 0 and no line images on every replica
     int mc_grid = 1;
     int mc_wide = 1;                 // one replica: the 512-thread Metropolis kernel
     hipGraph_t graph = nullptr;
@@ -281,11 +281,11 @@ static bhmc_status check_params(const bhmc_params& P, int64_t n) {
     return BHMC_OK;
 }
 
-// The multiple-image model is evaluated by bhmc_energy (and bhmc_energy_noalloc) only.
-static bhmc_status energy_only(const bhmc_tree* t, const char* what) {
+// The multiple-image model has energies and moves, not the gradient.
+static bhmc_status no_line_images(const bhmc_tree* t, const char* what) {
     for (const bhmc_params& P : t->params)
         if (P.line_images > 0)
-            return fail(BHMC_EINVAL, "%s: the multiple-image model (line_images > 0) supports bhmc_energy only", what);
+            return fail(BHMC_EINVAL, "%s: the multiple-image model (line_images > 0) has no gradient", what);
     return BHMC_OK;
 }
 
@@ -555,7 +555,7 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     t->arena2.assign(R, nullptr);
     t->ops = bhmc::eval_ops(t->p);
     for (int r = 0; r < R; ++r)
-        if (params[r].n0 != 0) t->all_n0_zero = false;
+        if (params[r].n0 != 0 || params[r].line_images > 0) t->rounds_ok = false;
     std::vector<long long> off(R);
     long long acc = 0;
     for (int r = 0; r < R; ++r) { fill_rep(t->host[r], params[r], n_per[r]); off[r] = acc; acc += n_per[r]; }
@@ -730,7 +730,7 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* dEdr_dev, double* dEdq_dev,
                                         double* E_host) {
     bhmc_status st = check_rep(t, replica);
-    if (st || (st = energy_only(t, "bhmc_energy_grad"))) return st;
+    if (st || (st = no_line_images(t, "bhmc_energy_grad"))) return st;
     if (!dEdr_dev || !dEdq_dev) return fail(BHMC_EINVAL, "null gradient output");
     if (!t->ops->grad) return fail(BHMC_EINVAL, "gradient not available for p = %d", t->p);
     const Rep& h = t->host[replica];
@@ -804,9 +804,7 @@ extern "C" bhmc_status bhmc_delta_energy(bhmc_tree* tree, int64_t i, const doubl
                                          int32_t* reason_host) {
     bhmc::MoveIO io;
     if (!tree) return fail(BHMC_EINVAL, "null tree");
-    bhmc_status st = energy_only(tree, "bhmc_delta_energy");
-    if (st) return st;
-    st = run_move(tree, i, r_new, 0, io);
+    bhmc_status st = run_move(tree, i, r_new, 0, io);
     if (st) return st;
     if (dE_host) *dE_host = io.reason ? HUGE_VAL : io.dE;
     if (reason_host) *reason_host = io.reason;
@@ -816,9 +814,7 @@ extern "C" bhmc_status bhmc_delta_energy(bhmc_tree* tree, int64_t i, const doubl
 extern "C" bhmc_status bhmc_commit_move(bhmc_tree* tree, int64_t i, const double* r_new) {
     bhmc::MoveIO io;
     if (!tree) return fail(BHMC_EINVAL, "null tree");
-    bhmc_status st = energy_only(tree, "bhmc_commit_move");
-    if (st) return st;
-    st = run_move(tree, i, r_new, 1, io);
+    bhmc_status st = run_move(tree, i, r_new, 1, io);
     if (st) return st;
     if (io.reason == 1) return fail(BHMC_EINVAL, "the move leaves the confinement");
     if (io.reason == 2) return fail(BHMC_EOVERLAP, "the move overlaps a hard core");
@@ -828,7 +824,7 @@ extern "C" bhmc_status bhmc_commit_move(bhmc_tree* tree, int64_t i, const double
 
 // Moves per round the handle's Metropolis launches take (1 = the move-by-move kernel).
 static int rounds_of(const bhmc_tree* t) {
-    if (t->moves_per_round == 1 || !t->all_n0_zero) return 1;
+    if (t->moves_per_round == 1 || !t->rounds_ok) return 1;
     const int cap = t->ops->moves_per_round;
     return t->moves_per_round > 1 && t->moves_per_round < cap ? t->moves_per_round : cap;
 }
@@ -887,7 +883,7 @@ static bhmc_status run_replica_until_done(bhmc_tree* t, int r, const bhmc::McArg
 extern "C" bhmc_status bhmc_mc_run(bhmc_tree* t, int32_t replica, uint64_t seed, uint64_t move0,
                                    int64_t n_moves, double step, uint8_t* accept_dev, bhmc_stats* stats_host) {
     bhmc_status st = check_rep(t, replica);
-    if (st || (st = energy_only(t, "bhmc_mc_run"))) return st;
+    if (st) return st;
     if (n_moves < 0 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad n_moves or step");
     if ((st = download(t))) return st;
     Rep& h = t->host[replica];
@@ -971,8 +967,8 @@ extern "C" bhmc_status bhmc_batch_sweep(bhmc_tree* t, uint64_t seed, int32_t n_s
                                         int32_t use_graph, bhmc_stats* stats_host) {
     if (!t) return fail(BHMC_EINVAL, "null tree");
     if (n_sweeps < 0 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad n_sweeps or step");
-    bhmc_status st = energy_only(t, "bhmc_batch_sweep");
-    if (st || (st = download(t))) return st;
+    bhmc_status st = download(t);
+    if (st) return st;
     for (int r = 0; r < t->R; ++r) {
         t->host[r].move_next = t->host[r].move_end;  // sweeps continue from the chain's end
         t->host[r].mc_status = 0;
@@ -1037,8 +1033,8 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
                                            int32_t* choice, float* ms_out) {
     if (!t) return fail(BHMC_EINVAL, "null tree");
     if (trial_moves < 1 || !std::isfinite(step)) return fail(BHMC_EINVAL, "bad trial_moves or step");
-    bhmc_status st = energy_only(t, "bhmc_batch_autotune");
-    if (st || (st = download(t))) return st;
+    bhmc_status st = download(t);
+    if (st) return st;
     for (int r = 0; r < t->R; ++r)
         if (t->host[r].move_end != 0 || t->host[r].stats[0] != 0)
             return fail(BHMC_EINVAL, "autotune needs replicas as built (replica %d has moved)", r);
@@ -1069,7 +1065,7 @@ extern "C" bhmc_status bhmc_batch_autotune(bhmc_tree* t, uint64_t seed, double s
     int best = -1;
     const int nshape = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
     // moves per round (targets per shared traversal): one at a time, half the most, the most
-    const int cap = t->all_n0_zero ? t->ops->moves_per_round : 1;
+    const int cap = t->rounds_ok ? t->ops->moves_per_round : 1;
     const int tiles[kAutotuneTiles] = {1, cap / 2 > 1 ? cap / 2 : 0, cap > 1 ? cap : 0};
     const int saved_mpr = t->moves_per_round;
     if (ms_out)

@@ -188,7 +188,7 @@ k_count(Rep* reps, const int* rep_list) {
         R.depth = depth;
         // sum_leaves max(count, cap) <= nsrc + nleaf * leaf_cap; every slot index must fit an int
         const long long pool = (long long)R.slack * ((long long)R.nsrc + (long long)R.nleaf * R.leaf_cap) +
-                               2ll * R.nleaf;
+                               (2ll + R.nline) * R.nleaf;
         if (pool > 0x7FFFFFFFll - 64) {
             R.pool = 0;
             R.status = -4;
@@ -266,7 +266,8 @@ k_topology(Rep* reps, const int* rep_list) {
                 const int leaf = leaf0 + (int)(ex >> 32);
                 R.lcell[leaf] = c;
                 const int cnt = e - b;
-                const int cap = R.slack * (cnt > R.leaf_cap ? cnt : R.leaf_cap) + 2;
+                // + 2 + M: one move inserts at most the ion and its 1 + M images
+                const int cap = R.slack * (cnt > R.leaf_cap ? cnt : R.leaf_cap) + 2 + R.nline;
                 R.lcap[leaf] = cap;
                 R.cm[c] = make_int4(cnt, -1 - leaf, -1, cap);
             }

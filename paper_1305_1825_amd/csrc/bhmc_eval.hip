@@ -856,6 +856,55 @@ __device__ int traverse_mc(const Rep& R, Trav<2, BLOCK>& S, int* cnt2, Hook&& ho
     return level;
 }
 
+// sum_{s <= p} P_s(cos psi) |d|^s / |R|^(s+1), psi the angle between d and -R: the
+// expansion of eq. 3.3 of one unit point source at c + d seen from c - R, order by
+// order equal to sum_{|n| <= p} T_n(R) d^n.  With A_s = P_s(cos psi) |d|^s |R|^s,
+// (s + 1) A_{s+1} = (2s + 1) (-d.R) A_s - s |d|^2 |R|^2 A_{s-1}.
+__device__ __forceinline__ double point_expansion(double Rx, double Ry, double Rz, double dx, double dy, double dz) {
+    const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    const double ir = rsqrt_nr(r2);
+    const double irr = ir * ir;
+    const double c1 = -(dx * Rx + dy * Ry + dz * Rz);
+    const double c2 = (dx * dx + dy * dy + dz * dz) * r2;
+    double a0 = 1.0, a1 = c1;
+    double sc = ir;               // |R|^-(2s+1)
+    double v = a0 * sc;
+    if (P >= 1) { sc *= irr; v = fma(a1, sc, v); }
+#pragma unroll
+    for (int s = 1; s < P; ++s) {
+        const double a2 = ((2.0 * s + 1.0) * c1 * a1 - (double)s * c2 * a0) / (s + 1.0);
+        a0 = a1; a1 = a2;
+        sc *= irr;
+        v = fma(a1, sc, v);
+    }
+    return v;
+}
+
+// What a unit source at sc adds to the potential at (x, y, z) through the tree when
+// the traversal keeps it as an ordinary source (N_0 = 0): walk its root path from the
+// top; the first cell passing the MAC takes it through its expansion, otherwise its
+// leaf takes it directly.  bad is set (and 0 returned) where a link is broken.
+__device__ __forceinline__ double walk_value(const Rep& R, double4 sc, double x, double y, double z, int& bad) {
+    const uint64_t key = morton_key(R, sc.x, sc.y, sc.z);
+    int c = 0;
+    for (int level = 0; level < kMaxLevels; ++level) {
+        if (c < 0 || c >= R.ncell) break;
+        const double4 g = R.cgeo[c];
+        const double dx = g.x - x, dy = g.y - y, dz = g.z - z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (3.0 * (g.w * g.w) <= R.theta2 * d2) return point_expansion(dx, dy, dz, sc.x - g.x, sc.y - g.y, sc.z - g.z);
+        const int link = R.cm[c].y;
+        if (link < 0) {
+            const double ex = x - sc.x, ey = y - sc.y, ez = z - sc.z;
+            return rsqrt_nr(ex * ex + ey * ey + ez * ez);
+        }
+        if (link + 8 > R.ncell) break;
+        c = link + key_digit(key, level + 1);
+    }
+    bad = 1;
+    return 0.0;
+}
+
 // ------------------------------------------------------------ one Monte Carlo move
 constexpr int kMaxPathCells = 4 * kMaxLevels;
 constexpr int kPowCells = 24;  // longer path-cell lists build their monomials by repeated products
@@ -919,6 +968,199 @@ __device__ __forceinline__ void prefetch_stage(const Rep& R, McShared& MS, int j
         MS.self_pidx[j] = gload(R.pidx + m.z + MS.tr[j].y);
         MS.pf_stage[j] = 3;
     }
+}
+
+// ------------------------------------------------------------ line images of the mover
+// The multiple-image model gives each ion M line-image sources (2n + m n + i) besides
+// its Kelvin image.  A move keeps the mover's own line images in its traversal as
+// ordinary sources and takes each back out of both potentials where the traversal met
+// it (lines_correct); an accepted move then checks every leaf it fills (lines_prepare)
+// and moves the line images after the ion and its image, in source order, as the
+// local modification of Sec. 3.3 (lines_commit).  The work arrays sit in the frontier
+// buffer, which the traversal no longer needs by then.
+constexpr int kLineContrib = 16;  // old and new position of up to 8 line images
+struct LineWork {
+    double px[kLineContrib], py[kLineContrib], pz[kLineContrib], pq[kLineContrib];  // 2m: old, 2m + 1: new
+    double corr[2];                              // per target: what the mover's line images added
+    int path[kLineContrib][kMaxLevels];          // root path of each contribution
+    int plen[kLineContrib];
+    int cnt[8], cap[8];                          // count and capacity of each new leaf
+    int ok, nlist;
+    int list_cell[kLineContrib * kMaxLevels];    // distinct path cells
+    uint32_t list_mask[kLineContrib * kMaxLevels];  // bit j: contribution j applies; bit 16: internal cell
+};
+constexpr uint32_t kLineInternal = 1u << 16;
+
+template <int BLOCK>
+__device__ __forceinline__ LineWork& line_work(Trav<2, BLOCK>& S) {
+    static_assert(sizeof(LineWork) <= sizeof(S.front), "the line-image work arrays must fit the frontier buffer");
+    return *reinterpret_cast<LineWork*>(&S.front[0][0]);
+}
+
+// Lanes 2m and 2m + 1 of the first wave walk line image m's root path from the old and
+// the new position of the mover; LW.corr[t] receives the sum over m.
+template <int BLOCK>
+__device__ __forceinline__ void lines_correct(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i) {
+    LineWork& LW = line_work(S);
+    if (wave_id() == 0) {
+        const int lane = lane_id(), t = lane & 1, m = lane >> 1;
+        double v = 0.0;
+        if (m < R.nline) {
+            const double4 x = MS.contrib[t];
+            const double4 sc = R.src[2 * R.n + m * R.n + i];
+            int bad = 0;
+            v = sc.w * walk_value(R, sc, x.x, x.y, x.z, bad);
+            if (bad) MS.err = kErrPathCell;
+        }
+        const double c0 = wave_sum(t == 0 ? v : 0.0), c1 = wave_sum(t == 1 ? v : 0.0);
+        if (lane == 0) { LW.corr[0] = c0; LW.corr[1] = c1; }
+    }
+    __syncthreads();
+}
+
+// Root paths of the old and new line images (thread 2m + k, k = 1 for the new one), then
+// on one thread the capacity check of all 2 + M moved sources in commit order: each one's
+// new leaf with the counts the earlier ones leave behind.
+template <int BLOCK>
+__device__ __forceinline__ void lines_prepare(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i) {
+    LineWork& LW = line_work(S);
+    const int tid = threadIdx.x, M = R.nline;
+    if (tid < 2 * M) {
+        const int m = tid >> 1, isnew = tid & 1, s = 2 * R.n + m * R.n + i;
+        double4 p;
+        if (isnew) {  // placed as the build places it, from the new Kelvin image
+            const double4 k = MS.contrib[3];
+            p = make_double4(R.line_t[m] * k.x, R.line_t[m] * k.y, R.line_t[m] * k.z, R.line_c[m] * k.w);
+        } else {
+            p = R.src[s];
+        }
+        LW.px[tid] = p.x; LW.py[tid] = p.y; LW.pz[tid] = p.z; LW.pq[tid] = p.w;
+        const uint64_t key = morton_key(R, p.x, p.y, p.z);
+        int c = 0, len = 0;
+        bool leaf = false;
+        for (int level = 0; level < kMaxLevels; ++level) {
+            if (c < 0 || c >= R.ncell) break;
+            LW.path[tid][level] = c;
+            len = level + 1;
+            const int4 cm = R.cm[c];
+            if (cm.y < 0) {
+                leaf = true;
+                if (isnew) { LW.cnt[m] = cm.x; LW.cap[m] = cm.w; }
+                break;
+            }
+            if (cm.y + 8 > R.ncell) break;
+            c = cm.y + key_digit(key, level + 1);
+        }
+        if (!leaf) { MS.err = kErrPathCell; len = 1; LW.path[tid][0] = 0; }
+        LW.plen[tid] = len;
+        if (leaf && !isnew && R.track[s].x != c) MS.err = kErrCommitSlot;  // the tracked leaf must be this one
+    }
+    __syncthreads();
+    if (tid == 0 && !MS.err) {
+        int lo[2 + 8], ln[2 + 8], cnt[2 + 8], cap[2 + 8];
+        lo[0] = MS.tr[0].x; ln[0] = MS.path[1][MS.plen[1] - 1]; cnt[0] = MS.lm_new[0].x; cap[0] = MS.lm_new[0].w;
+        lo[1] = MS.tr[1].x; ln[1] = MS.path[3][MS.plen[3] - 1]; cnt[1] = MS.lm_new[1].x; cap[1] = MS.lm_new[1].w;
+        for (int m = 0; m < M; ++m) {
+            lo[2 + m] = LW.path[2 * m][LW.plen[2 * m] - 1];
+            ln[2 + m] = LW.path[2 * m + 1][LW.plen[2 * m + 1] - 1];
+            cnt[2 + m] = LW.cnt[m]; cap[2 + m] = LW.cap[m];
+        }
+        bool ok = true;
+        for (int k = 0; k < 2 + M; ++k) {
+            if (ln[k] == lo[k]) continue;
+            int c = cnt[k];
+            for (int e = 0; e < k; ++e) {
+                if (ln[e] == lo[e]) continue;
+                if (ln[e] == ln[k]) c += 1;
+                if (lo[e] == ln[k]) c -= 1;
+            }
+            if (c + 1 > cap[k]) ok = false;
+        }
+        LW.ok = ok;
+    }
+    __syncthreads();
+}
+
+// After the ion and its image: thread 0 moves the line images between leaf index arrays
+// in source order (delete = the last entry fills the hole; add = append), then every
+// thread repairs the moments and counts of the distinct cells of their 2M root paths,
+// applying to each cell, in order, old line image 0 (-), new line image 0 (+), old 1 ...
+template <int BLOCK>
+__device__ __forceinline__ void lines_commit(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i) {
+    LineWork& LW = line_work(S);
+    const int tid = threadIdx.x, M = R.nline, nc = 2 * M;
+    if (tid == 0) {
+        for (int m = 0; m < M; ++m) {
+            const int s = 2 * R.n + m * R.n + i;
+            const int lo = LW.path[2 * m][LW.plen[2 * m] - 1], ln = LW.path[2 * m + 1][LW.plen[2 * m + 1] - 1];
+            const double4 pn = make_double4(LW.px[2 * m + 1], LW.py[2 * m + 1], LW.pz[2 * m + 1], LW.pq[2 * m + 1]);
+            const int2 tr = R.track[s];
+            const int4 mo = R.cm[lo];
+            if (tr.x != lo || mo.y >= 0 || tr.y < 0 || tr.y >= mo.x || mo.z < 0 || mo.z + mo.x > R.pool) {
+                MS.err = kErrCommitSlot;
+                break;
+            }
+            if (ln != lo) {
+                const int last = mo.x - 1, k = tr.y;
+                if (k != last) {
+                    const int moved = R.pidx[mo.z + last];
+                    if (moved < 0 || moved >= R.nsrc) { MS.err = kErrCommitSource; break; }
+                    R.pool4[mo.z + k] = R.pool4[mo.z + last];
+                    R.pidx[mo.z + k] = moved;
+                    R.track[moved] = make_int2(lo, k);
+                }
+                R.cm[lo].x = last;
+                const int4 mn = R.cm[ln];
+                if (mn.y >= 0 || mn.x < 0 || mn.x + 1 > mn.w || mn.z < 0 || mn.z + mn.w > R.pool) {
+                    MS.err = kErrCommitLeaf;
+                    break;
+                }
+                R.pool4[mn.z + mn.x] = pn;
+                R.pidx[mn.z + mn.x] = s;
+                R.track[s] = make_int2(ln, mn.x);
+                R.cm[ln].x = mn.x + 1;
+            } else {
+                R.pool4[mo.z + tr.y] = pn;
+            }
+            R.src[s] = pn;
+        }
+        LW.nlist = 0;
+    }
+    __syncthreads();
+    for (int it = tid; it < nc * kMaxLevels; it += BLOCK) {
+        const int j = it / kMaxLevels, l = it % kMaxLevels;
+        if (l >= LW.plen[j]) continue;
+        const int c = LW.path[j][l];
+        bool owner = true;
+        for (int jj = 0; jj < j; ++jj)
+            if (l < LW.plen[jj] && LW.path[jj][l] == c) owner = false;
+        if (!owner) continue;
+        uint32_t mask = l < LW.plen[j] - 1 ? kLineInternal : 0u;
+        for (int jj = j; jj < nc; ++jj)
+            if (l < LW.plen[jj] && LW.path[jj][l] == c) mask |= 1u << jj;
+        const int slot = atomicAdd(&LW.nlist, 1);
+        LW.list_cell[slot] = c;
+        LW.list_mask[slot] = mask;
+    }
+    __syncthreads();
+    const int items = LW.nlist * NTERM;
+    for (int it = tid; it < items; it += BLOCK) {
+        const int li = it / NTERM, k = it % NTERM;
+        const int c = LW.list_cell[li];
+        const uint32_t mask = LW.list_mask[li];
+        const double4 g = R.cgeo[c];
+        double mk = R.M[(size_t)c * MSTR + k];
+        int dc = 0;
+        for (int j = 0; j < nc; ++j) {
+            if (!(mask & (1u << j))) continue;
+            const double v = mono(S.mi[k], LW.px[j] - g.x, LW.py[j] - g.y, LW.pz[j] - g.z);
+            if (j & 1) { mk = mk + LW.pq[j] * v; ++dc; } else { mk = mk - LW.pq[j] * v; --dc; }
+        }
+        R.M[(size_t)c * MSTR + k] = mk;
+        if (R.M32) R.M32[(size_t)c * MSTR + k] = (float)mk;
+        if (k == 0 && (mask & kLineInternal) && dc != 0) R.cm[c].x += dc;
+    }
+    __syncthreads();
 }
 
 // Local modification of Sec. 3.3 for an accepted move.  Thread 0 moves the
@@ -1209,14 +1451,25 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     }
     const double po = pot[0], pn = pot[1];
     if (S.overlap || S.coincide) { out.reason = 2; __syncthreads(); return out; }
+    double lc0 = 0.0, lc1 = 0.0;  // what the mover's own line images added at the two targets
+    if (R.nline > 0) {
+        lines_correct<BLOCK>(R, S, MS, i);
+        if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
+        lc0 = line_work(S).corr[0];
+        lc1 = line_work(S).corr[1];
+    }
     // the move's positions and alpha come back from LDS: no registers held across the traversal
     const double4 so = MS.contrib[0], sn = MS.contrib[1];
     const double q = so.w, l = R.l_B;
-    double dE = l * q * (pn - po);
+    double dE = R.nline > 0 ? l * q * ((pn - lc1) - (po - lc0)) : l * q * (pn - po);
     if (R.geom == 1) {
         const double rn2 = sn.x * sn.x + sn.y * sn.y + sn.z * sn.z;
         const double ro2 = so.x * so.x + so.y * so.y + so.z * so.z;
         if (imgs) dE += 0.5 * l * R.gamma * R.a * q * q * (1.0 / (rn2 - R.a2) - 1.0 / (ro2 - R.a2));
+        // own line images: c_m q_K at t_m r_K, |r - t_m r_K| = (r^2 - t_m a^2) / |r|
+        for (int m = 0; m < R.nline; ++m)
+            dE += 0.5 * l * R.line_c[m] * R.gamma * R.a * q * q *
+                  (1.0 / (rn2 - R.line_t[m] * R.a2) - 1.0 / (ro2 - R.line_t[m] * R.a2));
         if (R.Qc != 0.0) dE += l * R.Qc * q * (1.0 / sqrt(rn2) - 1.0 / sqrt(ro2));
     }
     out.dE = dE;
@@ -1224,6 +1477,7 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     if (mode == 1) acc = dE <= 0.0 || MS.alpha <= exp(-dE);
     else if (mode == 2) acc = true;
     if (!acc) { __syncthreads(); return out; }
+    if (R.nline > 0) lines_prepare<BLOCK>(R, S, MS, i);
     if (tid == BLOCK - 1) {  // a thread with no path-cell item above
         // the tracked leaves must be the leaves the old positions' keys lead to,
         // and the tracked slots must hold the movers
@@ -1245,12 +1499,14 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         } else {
             MS.err = kErrCommitSlot;
         }
+        if (R.nline > 0 && !line_work(S).ok) ok = false;  // the line images' leaves, checked in order
         MS.ok = ok;
     }
     __syncthreads();
     if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
     if (!MS.ok) { out.stop = -6; __syncthreads(); return out; }
     commit<BLOCK>(R, S, MS, i);
+    if (R.nline > 0 && !MS.err) lines_commit<BLOCK>(R, S, MS, i);
     if (MS.err) { out.stop = -8; out.detail = MS.err; }
     out.accepted = 1;
     return out;
@@ -1984,10 +2240,8 @@ void run_move(hipStream_t s, Rep* reps, int r, MoveIO* io) {
 }
 // Line images of the multiple-image model (one thread per ion, after k_energy): an
 // ion's own line images stay in its traversal as sources, so each is taken back out of
-// its potential and energy term where the traversal met it.  With N_0 = 0 the
-// traversal takes a source through the first cell of its root path that passes the MAC
-// (the expansion of eq. 3.3 of that one point source), else directly at its leaf.  The
-// ion's energy with its own line images, 1/2 q sum_m c_m q_K / |r - t_m r_K|, is added.
+// its potential and energy term where the traversal met it (walk_value).  The ion's
+// energy with its own line images, 1/2 q sum_m c_m q_K / |r - t_m r_K|, is added.
 __global__ void __launch_bounds__(256) k_eline(Rep* reps, int r, double* phi, double* eterm) {
     const Rep& R = reps[r];
     const int ion = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1996,27 +2250,9 @@ __global__ void __launch_bounds__(256) k_eline(Rep* reps, int r, double* phi, do
     double sub = 0.0;
     for (int m = 0; m < R.nline; ++m) {
         const double4 sc = R.src[2 * R.n + m * R.n + ion];
-        const uint64_t key = morton_key(R, sc.x, sc.y, sc.z);
-        double v = 0.0;
-        int c = 0;
-        for (int level = 0;; ++level) {
-            if (c < 0 || c >= R.ncell || level > kMaxDepth) { reps[r].err_detail = kErrPathCell; v = __builtin_nan(""); break; }
-            const double4 g = R.cgeo[c];
-            const double dx = g.x - si.x, dy = g.y - si.y, dz = g.z - si.z;
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            if (3.0 * (g.w * g.w) <= R.theta2 * d2) {
-                v = point_expansion(dx, dy, dz, sc.x - g.x, sc.y - g.y, sc.z - g.z);
-                break;
-            }
-            const int link = R.cm[c].y;
-            if (link < 0) {
-                const double ex = si.x - sc.x, ey = si.y - sc.y, ez = si.z - sc.z;
-                v = rsqrt_nr(ex * ex + ey * ey + ez * ez);
-                break;
-            }
-            if (link + 8 > R.ncell) { reps[r].err_detail = kErrChildLink; v = __builtin_nan(""); break; }
-            c = link + key_digit(key, level + 1);
-        }
+        int bad = 0;
+        double v = walk_value(R, sc, si.x, si.y, si.z, bad);
+        if (bad) { reps[r].err_detail = kErrPathCell; v = __builtin_nan(""); }
         sub += sc.w * v;
     }
     const double r2 = si.x * si.x + si.y * si.y + si.z * si.z;

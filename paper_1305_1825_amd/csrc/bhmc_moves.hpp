@@ -545,30 +545,6 @@ __device__ void traverse_mb(const Rep& R, BTrav<BLOCK>& S, BMoves& MV, Hook&& ho
     }
 }
 
-// sum_{s <= p} P_s(cos psi) |d|^s / |R|^(s+1), psi the angle between d and -R: the
-// expansion of eq. 3.3 of one unit point source at c + d seen from c - R, order by
-// order equal to sum_{|n| <= p} T_n(R) d^n.  With A_s = P_s(cos psi) |d|^s |R|^s,
-// (s + 1) A_{s+1} = (2s + 1) (-d.R) A_s - s |d|^2 |R|^2 A_{s-1}.
-__device__ __forceinline__ double point_expansion(double Rx, double Ry, double Rz, double dx, double dy, double dz) {
-    const double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-    const double ir = rsqrt_nr(r2);
-    const double irr = ir * ir;
-    const double c1 = -(dx * Rx + dy * Ry + dz * Rz);
-    const double c2 = (dx * dx + dy * dy + dz * dz) * r2;
-    double a0 = 1.0, a1 = c1;
-    double sc = ir;               // |R|^-(2s+1)
-    double v = a0 * sc;
-    if (P >= 1) { sc *= irr; v = fma(a1, sc, v); }
-#pragma unroll
-    for (int s = 1; s < P; ++s) {
-        const double a2 = ((2.0 * s + 1.0) * c1 * a1 - (double)s * c2 * a0) / (s + 1.0);
-        a0 = a1; a1 = a2;
-        sc *= irr;
-        v = fma(a1, sc, v);
-    }
-    return v;
-}
-
 // What contribution cc of move j adds (per unit charge) to the potential at x through
 // the tree: walk its root path from the top; the first cell passing the MAC takes it
 // through its expansion, otherwise its leaf takes it directly.

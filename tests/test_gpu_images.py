@@ -7,7 +7,10 @@ sources, their keys and the tree must agree bit for bit.  The GPU energy keeps a
 ion's own line images in its traversal and takes each back out where the
 traversal met it; with N_0 = 0 that equals the oracle's exact exclusion up to
 rounding, so energies and potentials are held to the tolerances of the one-image
-model (1e-12 of their scale).  Every other evaluation rejects the model."""
+model (1e-12 of their scale).  Moves (which move the ion, its Kelvin image and its
+line images) are held to the one-image model's parity: energy changes within
+1e-11, accept streams, positions and leaf index arrays bit-exact, moments within
+1e-11.  The gradient rejects the model."""
 import numpy as np
 import pytest
 
@@ -76,14 +79,144 @@ def test_rebuild_keeps_the_energy():
     g.close()
 
 
-def test_other_evaluations_reject_the_model():
+def cell_map(cells):
+    return {(int(l), int(k)): i for i, (l, k) in enumerate(zip(cells["level"], cells["kmin"]))}
+
+
+def assert_same_slots_and_moments(g, o, p):
+    """Leaf index arrays bit-exact; moments within 1e-11 of sum |q| (sqrt(3) h)^|n|."""
+    cg, co = g.cells(), o.cells()
+    mg, mo = cell_map(cg), cell_map(co)
+    assert set(mg) == set(mo)
+    members = g.leaf_members()
+    lg, lo = g.leaves(), o.leaves()
+    gl = {(int(cg["level"][c]), int(cg["kmin"][c])): members[l] for l, c in enumerate(lg["cell"])}
+    for l in range(len(lo["cell"])):
+        c = lo["cell"][l]
+        key = (int(co["level"][c]), int(co["kmin"][c]))
+        assert np.array_equal(gl[key], o.leaf_slots(l)), "leaf %s slots differ" % (key,)
+    order = O.multi_indices(p).sum(axis=1)
+    tot = np.sum(np.abs(o.sources()[3]))
+    for key, io in mo.items():
+        scale = tot * (np.sqrt(3.0) * co["geo"][io, 3]) ** order + 1e-300
+        assert np.all(np.abs(cg["M"][mg[key]] - co["M"][io]) <= 1e-11 * scale), key
+
+
+@pytest.mark.parametrize("M,p,theta", [(2, 4, 0.5), (8, 6, 0.4), (4, 8, 0.0)])
+def test_energy_change_matches_oracle(M, p, theta):
+    P, x, y, z, q = system(1500, M, theta=theta, p=p)
+    say("line images delta M=%d p=%d theta=%g" % (M, p, theta))
+    g, o = bhmc.Tree(P, x, y, z, q), O.Tree(P, x, y, z, q)
+    n = len(x)
+    checked = 0
+    for m in range(60):
+        i, d, _ = O.draw_move(321, 0, m, n, 1.5)
+        rn = np.array([x[i], y[i], z[i]]) + d
+        dEo, ro = o.delta(i, rn)
+        dEg, rg = g.delta_energy(i, rn)
+        assert rg == ro
+        if ro:
+            assert np.isinf(dEg)
+            continue
+        phi = abs(o.phi([x[i], y[i], z[i]], [i, n + i] + [2 * n + k * n + i for k in range(M)]))
+        tol = 1e-11 * max(abs(dEo), P["l_B"] * abs(q[i]) * phi)
+        assert abs(dEg - dEo) <= tol, (m, i, dEg, dEo)
+        checked += 1
+    assert checked > 40
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["M2_p5", "M8_p6", "tight_slots"])
+def test_chain_bit_exact_against_oracle(case):
+    """Accept stream, statistics (rebuilds included), positions and leaf index arrays
+    bit-exact; moments and the energy after the chain to their tolerances."""
+    if case == "M2_p5":
+        (P, x, y, z, q), moves = system(1500, 2, theta=0.4, p=5), 1500
+    elif case == "M8_p6":
+        (P, x, y, z, q), moves = system(1500, 8, theta=0.5, p=6), 1000
+    else:  # leaves fill up: the capacity check over all 2 + M moved sources, and rebuilds
+        P, x, y, z, q = system(600, 2, theta=0.5, p=5)
+        P = dict(P, leaf_cap=4, slot_slack=1, max_depth=2)
+        moves = 3000
+    step = 2.0 if case == "tight_slots" else 1.0
+    say("line images chain", case)
+    g, o = bhmc.Tree(P, x, y, z, q), O.Tree(P, x, y, z, q)
+    assert g.set_moves_per_round(0) == 1  # one move per traversal with line images
+    rg = g.mc_run(seed=4, n_moves=moves, step=step, accept_bits=True)
+    ro = o.mc_run(seed=4, replica=0, move0=0, n_moves=moves, step=step)
+    first = np.nonzero(rg["accept"].cpu().numpy() != ro["accept"])[0]
+    assert len(first) == 0, "accept streams part at move %d" % first[0]
+    st = ro["stats"]
+    assert rg["accepted"] == st[0] and rg["rejected_wall"] == st[1] and rg["rejected_overlap"] == st[2]
+    assert rg["rebuilds"] == st[3]
+    if case == "tight_slots":
+        assert st[3] > 0
+    n = len(x)
+    xs, ys, zs, _ = (t.cpu().numpy() for t in g.state())
+    xo, yo, zo, _ = o.sources()
+    assert np.array_equal(xs, xo[:n]) and np.array_equal(ys, yo[:n]) and np.array_equal(zs, zo[:n])
+    assert_same_slots_and_moments(g, o, P["p"])
+    Eg, Eo = g.energy(), o.energy()
+    assert abs(Eg - Eo) <= 1e-11 * abs(Eo)
+    g.close()
+
+
+def test_chain_at_theta_zero_is_the_direct_chain():
+    P, x, y, z, q = system(700, 5, theta=0.0, p=3)
+    g = bhmc.Tree(P, x, y, z, q)
+    rg = g.mc_run(seed=9, n_moves=1500, step=1.0, accept_bits=True)
+    rd = O.direct_mc_run(P, x, y, z, q, 9, 0, 0, 1500, 1.0)
+    assert np.array_equal(rg["accept"].cpu().numpy(), rd["accept"])
+    xs, ys, zs, _ = (t.cpu().numpy() for t in g.state())
+    assert np.array_equal(xs, rd["x"]) and np.array_equal(ys, rd["y"]) and np.array_equal(zs, rd["z"])
+    g.close()
+
+
+def test_commit_move_api_matches_oracle():
+    P, x, y, z, q = system(800, 3, theta=0.5, p=4)
+    g, o = bhmc.Tree(P, x, y, z, q), O.Tree(P, x, y, z, q)
+    n = len(x)
+    done = 0
+    for m in range(80):
+        i, d, _ = O.draw_move(77, 0, m, n, 1.0)
+        xo, yo, zo, _ = o.sources()
+        rn = np.array([xo[i], yo[i], zo[i]]) + d
+        _, reason = o.delta(i, rn)
+        if reason:
+            continue
+        o.commit(i, rn)
+        g.commit_move(i, rn)
+        done += 1
+    assert done > 60
+    assert_same_slots_and_moments(g, o, P["p"])
+    g.close()
+
+
+def test_batched_replicas_with_line_images_equal_single_chains():
+    sizes = [300, 500, 420]
+    reps = []
+    for r, n in enumerate(sizes):
+        c = W.config_colloid_10k(n=n, p=4)
+        reps.append((dict(c["params"], theta=0.5, p=4, line_images=r + 1), c["x"], c["y"], c["z"], c["q"]))
+    cat = [np.concatenate([rp[k] for rp in reps]) for k in range(1, 5)]
+    g = bhmc.Tree([rp[0] for rp in reps], *cat, n_per_replica=sizes)
+    say("  autotune", g.autotune(seed=5, step=1.0, trial_moves=100))
+    stats = g.batch_sweep(seed=11, n_sweeps=2, step=1.0, use_graph=True)
+    for r, (P, x, y, z, q) in enumerate(reps):
+        o = O.Tree(P, x, y, z, q)
+        ro = o.mc_run(seed=11, replica=r, move0=0, n_moves=2 * sizes[r], step=1.0)
+        assert stats[r]["moves"] == 2 * sizes[r] and stats[r]["accepted"] == ro["stats"][0], r
+        xs, ys, zs, _ = (t.cpu().numpy() for t in g.state(r))
+        xo, yo, zo, _ = o.sources()
+        n = sizes[r]
+        assert np.array_equal(xs, xo[:n]) and np.array_equal(ys, yo[:n]) and np.array_equal(zs, zo[:n]), r
+    g.close()
+
+
+def test_gradient_rejects_the_model():
     P, x, y, z, q = system(300, 2)
     g = bhmc.Tree(P, x, y, z, q)
-    rn = np.array([x[0], y[0], z[0]]) + 0.1
-    for call in (lambda: g.mc_run(seed=0, n_moves=10, step=1.0), lambda: g.delta_energy(0, rn),
-                 lambda: g.commit_move(0, rn), lambda: g.energy_grad(),
-                 lambda: g.batch_sweep(seed=0, n_sweeps=1, step=1.0, use_graph=False)):
-        with pytest.raises(bhmc.BhmcError) as e:
-            call()
-        assert "supports bhmc_energy only" in str(e.value)
+    with pytest.raises(bhmc.BhmcError) as e:
+        g.energy_grad()
+    assert "has no gradient" in str(e.value)
     g.close()
