@@ -234,6 +234,42 @@ def accuracy(P, x, y, z, q):
     return {"E_4_1": e41, "E_rel": erel, "E_tree": E_tree, "E_direct": E_dir, "meets_1e-4": max(e41, erel) <= 1e-4}
 
 
+def run_lines(c, moves, M=4, p=6, calls=5):
+    """The headline system with M line images per ion besides each Kelvin image, at order p
+    (the headline's theta): the chain one move per traversal (kernel time) beside the same
+    chain with the Kelvin image alone, the energy evaluation, and the accuracy of both ends
+    of the chain against the same model summed directly."""
+    import torch
+    from paper_1305_1825_amd import bhmc
+    P = dict(c["params"], line_images=M, p=p)
+    x, y, z, q = c["x"], c["y"], c["z"], c["q"]
+    ch = chain_kernel_rate(P, x, y, z, q, moves=moves, seed=c["seed"], step=c["step"])
+    ck = chain_kernel_rate(dict(P, line_images=0), x, y, z, q, moves=moves, seed=c["seed"], step=c["step"])
+    t = bhmc.Tree(P, x, y, z, q)
+    t.energy()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(calls):
+        t.energy()
+    e1.record(s)
+    e1.synchronize()
+    energy_ms = e0.elapsed_time(e1) / calls
+    t.mc_run(seed=c["seed"], n_moves=moves, step=c["step"])
+    fx, fy, fz, fq = (v.cpu().numpy() for v in t.state())
+    t.close()
+    a0, a1 = accuracy(P, x, y, z, q), accuracy(P, fx, fy, fz, fq)
+    return {"workload": "as the headline at p=%d, plus %d line-image sources per ion "
+                        "(sigma = eps_out/(eps_in+eps_out))" % (p, M),
+            "sources": (2 + M) * len(x), "chain_moves_per_s": ch["moves_per_s"], "chain_moves": moves,
+            "chain_accepted": ch["accepted"], "kernel": "k_mc<512> (one move per traversal)",
+            "kelvin_only_chain_moves_per_s": ck["moves_per_s"],
+            "energy_ms": energy_ms,
+            "accuracy_start": {k: a0[k] for k in ("E_4_1", "E_rel", "meets_1e-4")},
+            "accuracy_end": {k: a1[k] for k in ("E_4_1", "E_rel", "meets_1e-4")}}
+
+
 def timed_sweeps(R, sweeps, params, seed=0):
     """One autotuned handle of the R replicas: a warm-up sweep (which builds the graph),
     then `sweeps` timed sweeps; and the accuracy on the smallest, median and largest replica."""
@@ -449,6 +485,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--no-stated", action="store_true", help="skip the theta=0.5, p=6 leg")
+    ap.add_argument("--no-lines", action="store_true", help="skip the multiple-image leg")
+    ap.add_argument("--line-moves", type=int, default=20000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB once with a plain device copy (the reference dispatch of the "
                          "HBM counter passes)")
@@ -547,6 +585,9 @@ def main():
             "accuracy_start": {k: a0[k] for k in ("E_4_1", "E_rel", "meets_1e-4")},
             "accuracy_end": {k: a1[k] for k in ("E_4_1", "E_rel", "meets_1e-4")},
             "gate_met": a0["meets_1e-4"] and a1["meets_1e-4"]}
+    if not args.no_lines:
+        log("the headline system with the multiple-image model (M = 4 line images per ion)")
+        out["line_images"] = run_lines(c, args.line_moves)
     if not args.no_batched:
         log("batched replicas")
         b = run_batched(256, args.batched_sweeps, GATED_REPLICAS)
