@@ -27,7 +27,7 @@
  *   - the multiple-image model of the dielectric sphere (Sec. 1 and Sec. 5
  *     name it without formulas): besides the Kelvin image, a line image from
  *     the sphere's centre to the Kelvin point, discretised by a Gauss-Jacobi
- *     rule; energies and Monte Carlo moves (no gradient).
+ *     rule (energies, moves and the gradient).
  *
  * Every floating-point expression whose outcome decides an integer (a key, a
  * MAC decision, a wall or overlap test, a Metropolis decision) is written left
@@ -60,7 +60,7 @@ typedef struct {
     double r_min, r_max; /* shell confinement (Sec. 4, spherical cell model)  */
     double hard_core;    /* contact distance tau (eq. 2.1)                    */
     int32_t slot_slack;  /* leaf slots = slack * max(count, leaf_cap) + 2 + M */
-    int32_t line_images; /* 0, or M line-image points per ion (no gradient)  */
+    int32_t line_images; /* 0, or M line-image points per ion (1..8)          */
 } orc_params;
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOUTSIDE = -2, ORC_ECAPACITY = -6 };
@@ -469,9 +469,10 @@ void orc_direct_phi(const orc_params *P, int64_t n, const double *x, const doubl
 void orc_direct_grad(const orc_params *P, int64_t n, const double *x, const double *y,
                      const double *z, const double *q, double *gx, double *gy, double *gz,
                      double *gq) {
-    if (P->line_images) return;  /* the multiple-image model has no gradient here */
     int shell = P->geom == 1, imgs = shell && P->images;
     double g = gamma_of(P), a = P->a, a2 = a * a;
+    orc_lines L;
+    lines_of(P, &L);
     for (int64_t i = 0; i < n; ++i) {
         nsum sx = {0, 0}, sy = {0, 0}, sz = {0, 0}, sq = {0, 0};
         double ri2 = x[i] * x[i] + y[i] * y[i] + z[i] * z[i];
@@ -492,6 +493,19 @@ void orc_direct_grad(const orc_params *P, int64_t n, const double *x, const doub
                 nadd(&sy, c * (rj2 * y[i] - a2 * y[j]));
                 nadd(&sz, c * (rj2 * z[i] - a2 * z[j]));
                 nadd(&sq, g * a * q[j] * iD12);
+                /* line image m of either ion: coefficient -sigma w_m on the kernel with
+                 * D_t = |r_i|^2 |r_j|^2 - 2 t a^2 r_i.r_j + t^2 a^4 */
+                double dot = x[i] * x[j] + y[i] * y[j] + z[i] * z[j];
+                for (int m = 0; m < L.M; ++m) {
+                    double tt = L.t[m], cm = -L.sigma * L.w[m];
+                    double Dt = ri2 * rj2 - 2.0 * tt * a2 * dot + tt * tt * a2 * a2;
+                    double iDt12 = 1.0 / sqrt(Dt), iDt32 = iDt12 / Dt;
+                    double ct = -cm * g * a * q[i] * q[j] * iDt32;
+                    nadd(&sx, ct * (rj2 * x[i] - tt * a2 * x[j]));
+                    nadd(&sy, ct * (rj2 * y[i] - tt * a2 * y[j]));
+                    nadd(&sz, ct * (rj2 * z[i] - tt * a2 * z[j]));
+                    nadd(&sq, cm * g * a * q[j] * iDt12);
+                }
             }
         }
         if (imgs) {
@@ -499,6 +513,13 @@ void orc_direct_grad(const orc_params *P, int64_t n, const double *x, const doub
             double c = -g * a * q[i] * q[i] / (den * den);
             nadd(&sx, c * x[i]); nadd(&sy, c * y[i]); nadd(&sz, c * z[i]);
             nadd(&sq, g * a * q[i] / den);
+            /* own line images: 1/2 c_m gamma a q^2 / (r^2 - t_m a^2) */
+            for (int m = 0; m < L.M; ++m) {
+                double cm = -L.sigma * L.w[m], dm = ri2 - L.t[m] * a2;
+                double cl = -cm * g * a * q[i] * q[i] / (dm * dm);
+                nadd(&sx, cl * x[i]); nadd(&sy, cl * y[i]); nadd(&sz, cl * z[i]);
+                nadd(&sq, cm * g * a * q[i] / dm);
+            }
         }
         if (shell && P->Q_center != 0.0) {
             double r = sqrt(ri2), ir3 = 1.0 / (ri2 * r);
@@ -1140,8 +1161,10 @@ static void grad_visit(const otree *t, int c, int tg, const int *ex, int nex, gs
 
 /* dE_tree/dr_i and dE_tree/dq_i for every ion; returns E_tree. */
 double orc_tree_grad(otree *t, double *gx, double *gy, double *gz, double *gq) {
-    if (t->P.line_images) return NAN;  /* the multiple-image model has no gradient here */
-    int ns = t->nsrc, n = t->n, nex = t->P.images ? 2 : 1;
+    int ns = t->nsrc, n = t->n, M = t->P.images ? t->P.line_images : 0;
+    int nex = t->P.images ? 2 + M : 1;
+    orc_lines L;
+    lines_of(&t->P, &L);
     gstate g;
     g.gx = (double *)calloc(ns, sizeof(double)); g.gy = (double *)calloc(ns, sizeof(double));
     g.gz = (double *)calloc(ns, sizeof(double)); g.gq = (double *)calloc(ns, sizeof(double));
@@ -1149,7 +1172,8 @@ double orc_tree_grad(otree *t, double *gx, double *gy, double *gz, double *gq) {
     g.mono = (double *)malloc(sizeof(double) * nterms_of(t->P.p + 1));
     int *buf = NULL, capb = 0;
     for (int i = 0; i < n; ++i) {
-        int ex[2] = {i, n + i};
+        int ex[10] = {i, n + i};  /* the ion and all of its images */
+        for (int m = 0; m < M; ++m) ex[2 + m] = 2 * n + m * n + i;
         grad_visit(t, 0, i, ex, nex, &g, &buf, &capb);
     }
     free(buf);
@@ -1160,15 +1184,21 @@ double orc_tree_grad(otree *t, double *gx, double *gy, double *gz, double *gq) {
         double Gx = g.gx[i], Gy = g.gy[i], Gz = g.gz[i], Gq = g.gq[i];
         if (t->P.images) {
             int s = n + i;
+            /* line image m sits at t_m r_K with charge c_m q_K: its gradient joins the
+             * Kelvin image's, weighted by t_m (position) and c_m (charge) */
+            double hx = g.gx[s], hy = g.gy[s], hz = g.gz[s], dqK = g.gq[s];
+            for (int m = 0; m < M; ++m) {
+                int sm = 2 * n + m * n + i;
+                hx += L.t[m] * g.gx[sm]; hy += L.t[m] * g.gy[sm]; hz += L.t[m] * g.gz[sm];
+                dqK += -L.sigma * L.w[m] * g.gq[sm];
+            }
             /* r_K = a^2 r / r^2: J = a^2 (I / r^2 - 2 r r^T / r^4), symmetric */
             double a2 = a * a, ir2 = 1.0 / r2, ir4 = ir2 * ir2;
-            double hx = g.gx[s], hy = g.gy[s], hz = g.gz[s];
             double rh = x * hx + y * hy + z * hz;
             Gx += a2 * (hx * ir2 - 2.0 * x * rh * ir4);
             Gy += a2 * (hy * ir2 - 2.0 * y * rh * ir4);
             Gz += a2 * (hz * ir2 - 2.0 * z * rh * ir4);
             /* q_K = gamma a q / r */
-            double dqK = g.gq[s];
             double c = -gam * a * q / (r2 * r);
             Gx += dqK * c * x; Gy += dqK * c * y; Gz += dqK * c * z;
             Gq += dqK * gam * a / r;
@@ -1177,6 +1207,13 @@ double orc_tree_grad(otree *t, double *gx, double *gy, double *gz, double *gq) {
             double cs = -l * gam * a * q * q / (den * den);
             Gx += cs * x; Gy += cs * y; Gz += cs * z;
             Gq += l * gam * a * q / den;
+            /* and of the own line images, 1/2 l_B c_m gamma a q^2 / (r^2 - t_m a^2) */
+            for (int m = 0; m < M; ++m) {
+                double cm = -L.sigma * L.w[m], dm = r2 - L.t[m] * a2;
+                double cl = -l * cm * gam * a * q * q / (dm * dm);
+                Gx += cl * x; Gy += cl * y; Gz += cl * z;
+                Gq += l * cm * gam * a * q / dm;
+            }
         }
         if (t->P.geom == 1 && t->P.Q_center != 0.0) {
             double ir3 = 1.0 / (r2 * r), Q = t->P.Q_center;

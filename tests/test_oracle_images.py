@@ -9,8 +9,9 @@ on the sphere.  The oracle represents it by the Kelvin image plus M points of a
 line image placed by a Gauss rule of the weight t^(sigma - 1) on [0, 1]; here the
 rule is pinned by its moments (and by Gauss-Legendre at sigma = 1), the image
 potential by the Legendre series itself, the treecode energy with line images by
-the direct sum, and a Monte Carlo move (which moves the ion, its Kelvin image and
-its line images) by the difference of direct energies and the direct-sum chain."""
+the direct sum, a Monte Carlo move (which moves the ion, its Kelvin image and its
+line images) by the difference of direct energies and the direct-sum chain, and the
+gradient by finite differences and the direct gradient."""
 import numpy as np
 import pytest
 from scipy.special import eval_legendre
@@ -208,12 +209,61 @@ def test_tree_chain_with_line_images_is_the_direct_chain(max_depth):
     assert np.array_equal(np.sort(seen), np.arange(len(xs)))
 
 
-def test_oracle_line_images_have_no_gradient():
+def _fd(E, arrs, i, comp, h):
+    a1 = [a.copy() for a in arrs]
+    a2 = [a.copy() for a in arrs]
+    a1[comp][i] += h
+    a2[comp][i] -= h
+    return (E(*a1) - E(*a2)) / (2 * h)
+
+
+@pytest.mark.parametrize("M", [2, 6])
+def test_direct_gradient_with_line_images_matches_finite_differences(M):
+    c = W.config_colloid_10k(n=120, p=2)
+    P = dict(c["params"], line_images=M)
+    arrs = [np.array(c[k], dtype=float) for k in "xyzq"]
+    g, gq = O.direct_grad(P, *arrs)
+    E = lambda *a: O.direct_energy(P, *a)
+    for i in range(0, 120, 17):
+        for comp in range(3):
+            assert _fd(E, arrs, i, comp, 1e-6) == pytest.approx(g[i, comp], abs=1e-6 * (abs(g[i, comp]) + 1.0))
+        assert _fd(E, arrs, i, 3, 1e-6) == pytest.approx(gq[i], abs=1e-6 * (abs(gq[i]) + 1.0))
+    # the line images change the gradient: the Kelvin image alone gives another one
+    gk, _ = O.direct_grad(dict(P, line_images=0), *arrs)
+    assert np.max(np.abs(gk - g)) > 1e-4 * np.max(np.abs(g))
+
+
+def test_tree_gradient_with_line_images():
+    """theta = 0: the treecode gradient is the direct one; theta = 0.5: it matches central
+    differences of the treecode energy (fresh builds), except where a shift moves a cell
+    across the MAC; the Euler identity in the charges holds (E is quadratic in them plus
+    the central charge's linear term)."""
+    c = W.config_colloid_10k(n=200, p=4)
+    P = dict(c["params"], line_images=3)
+    arrs = [np.array(c[k], dtype=float) for k in "xyzq"]
+    E0, g0, gq0 = O.Tree(dict(P, theta=0.0), *arrs).grad()
+    gd, gqd = O.direct_grad(P, *arrs)
+    assert np.allclose(g0, gd, rtol=0, atol=1e-11 * np.abs(gd).max())
+    assert np.allclose(gq0, gqd, rtol=0, atol=1e-11 * np.abs(gqd).max())
+    E, g, gq = O.Tree(P, *arrs).grad()
+    assert E == pytest.approx(O.Tree(P, *arrs).energy(), rel=1e-14)
+    x, y, z, q = arrs
+    Elin = P["l_B"] * P["Q_center"] * np.sum(q / np.sqrt(x * x + y * y + z * z))
+    assert np.dot(q, gq) == pytest.approx(2 * (E - Elin) + Elin, rel=1e-11)
+    Et = lambda *a: O.Tree(P, *a).energy()
+    rms, rmsq = np.sqrt(np.mean(g ** 2)), np.sqrt(np.mean(gq ** 2))
+    bad = 0
+    for i in range(0, 200, 23):
+        for comp in range(3):
+            if abs(_fd(Et, arrs, i, comp, 1e-6) - g[i, comp]) > 1e-6 * (abs(g[i, comp]) + rms):
+                bad += 1
+        assert _fd(Et, arrs, i, 3, 1e-6) == pytest.approx(gq[i], abs=1e-6 * (abs(gq[i]) + rmsq))
+    assert bad <= 1
+
+
+def test_oracle_line_images_parameters():
     c = W.config_colloid_10k(n=200, p=4)
     P = dict(c["params"], line_images=2)
-    t = O.Tree(P, c["x"], c["y"], c["z"], c["q"])
-    E, _, _ = t.grad()
-    assert np.isnan(E)
     with pytest.raises(Exception):
         O.Tree(dict(P, line_images=9), c["x"], c["y"], c["z"], c["q"])
     with pytest.raises(Exception):
