@@ -97,11 +97,11 @@ enum { BHMC_REASON_NONE = 0, BHMC_REASON_WALL = 1, BHMC_REASON_OVERLAP = 2 };
  *              eps_out / (eps_in + eps_out)); the line is replaced by the M-point
  *              Gauss rule of the weight t^(sigma-1) on [0, 1] (nodes t_m and
  *              weights w_m rounded to multiples of 2^-40): M more sources per
- *              ion, -sigma w_m q_K at t_m r_K, numbered 2n + m n + i.  The
- *              energy, energy change, commit and Monte Carlo calls evaluate it
- *              (a move then moves the ion, its Kelvin image and its M line
- *              images, in that order; the Metropolis calls take one move per
- *              traversal); bhmc_energy_grad returns BHMC_EINVAL.
+ *              ion, -sigma w_m q_K at t_m r_K, numbered 2n + m n + i.  Every
+ *              call evaluates it: a move moves the ion, its Kelvin image and
+ *              its M line images, in that order (the Metropolis calls then
+ *              take one move per traversal), and the gradient maps each line
+ *              image back to its ion through t_m r_K and -sigma w_m q_K.
  *   reserved   0.
  */
 typedef struct {
@@ -273,7 +273,8 @@ bhmc_status bhmc_set_launch_shape(bhmc_tree* tree, int32_t shape);
  * q_t q_j sum_n T_n(r_A - r_t) (r_j - r_A)^n of eq. 3.3 and each near pair
  * q_t q_j / |r_t - r_j| is differentiated in both its points and charges; the
  * images are mapped back to their ions by the chain rule through
- * q_K = gamma a q / |r|, r_K = a^2 r / |r|^2).  It uses the replica's current
+ * q_K = gamma a q / |r|, r_K = a^2 r / |r|^2, line images through t_m r_K and
+ * -sigma w_m q_K).  It uses the replica's current
  * moments, which equal a fresh evaluation from the current positions up to
  * rounding (bhmc_rebuild refreshes them); nothing of the traversal is stored.
  * Outputs: dEdr_dev (dev, 3n values, x y z per ion), dEdq_dev (dev, n

@@ -152,6 +152,7 @@ struct bhmc_tree {
     bool energy_bounded = false;     // energy / gradient launches keep their grid within the regions
     int moves_per_round = 0;         // 0: as many as the order allows; 1: the move-by-move kernel
     bool rounds_ok = true;           // the rounds kernel needs N_0 = 0 and no line images on every replica
+    bool has_lines = false;          // some replica has line images
     int mc_grid = 1;
     int mc_wide = 1;                 // one replica: the 512-thread Metropolis kernel
     hipGraph_t graph = nullptr;
@@ -278,14 +279,6 @@ static bhmc_status check_params(const bhmc_params& P, int64_t n) {
         if (!(sigma >= 0.5 && sigma <= 1.0)) return fail(BHMC_EINVAL, "line images need eps_in <= eps_out");
         if ((2 + P.line_images) * n > (1 << 23)) return fail(BHMC_EINVAL, "too many sources with line images");
     }
-    return BHMC_OK;
-}
-
-// The multiple-image model has energies and moves, not the gradient.
-static bhmc_status no_line_images(const bhmc_tree* t, const char* what) {
-    for (const bhmc_params& P : t->params)
-        if (P.line_images > 0)
-            return fail(BHMC_EINVAL, "%s: the multiple-image model (line_images > 0) has no gradient", what);
     return BHMC_OK;
 }
 
@@ -554,8 +547,10 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     t->arena1.assign(R, nullptr);
     t->arena2.assign(R, nullptr);
     t->ops = bhmc::eval_ops(t->p);
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r) {
+        if (params[r].line_images > 0) t->has_lines = true;
         if (params[r].n0 != 0 || params[r].line_images > 0) t->rounds_ok = false;
+    }
     std::vector<long long> off(R);
     long long acc = 0;
     for (int r = 0; r < R; ++r) { fill_rep(t->host[r], params[r], n_per[r]); off[r] = acc; acc += n_per[r]; }
@@ -730,7 +725,7 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* dEdr_dev, double* dEdq_dev,
                                         double* E_host) {
     bhmc_status st = check_rep(t, replica);
-    if (st || (st = no_line_images(t, "bhmc_energy_grad"))) return st;
+    if (st) return st;
     if (!dEdr_dev || !dEdq_dev) return fail(BHMC_EINVAL, "null gradient output");
     if (!t->ops->grad) return fail(BHMC_EINVAL, "gradient not available for p = %d", t->p);
     const Rep& h = t->host[replica];
@@ -756,7 +751,7 @@ extern "C" bhmc_status bhmc_energy_grad(bhmc_tree* t, int32_t replica, double* d
     w.rank = (int*)(t->gwork + lb + gb + tb);
     w.islot = (int*)(t->gwork + lb + gb + tb + ob);
     w.fcell = (int*)(t->gwork + lb + gb + tb + ob + ib);
-    w.ncell = h.ncell; w.nleaf = h.nleaf; w.nsrc = h.nsrc; w.n = n;
+    w.ncell = h.ncell; w.nleaf = h.nleaf; w.nsrc = h.nsrc; w.n = n; w.nline = h.nline;
     for (;;) {
         t->ops->grad(t->stream, t->reps, replica, w, dEdr_dev, dEdq_dev, t->eterm, energy_grid_bound(t));
         HIP_TRY(hipGetLastError());
@@ -779,7 +774,7 @@ static bhmc_status run_move(bhmc_tree* t, int64_t i, const double* r_new, int mo
     for (;;) {
         io = io_in;
         if ((st = h2d(t, t->io, &io, sizeof(io)))) return st;
-        t->ops->move(t->stream, t->reps, 0, t->io);
+        t->ops->move(t->stream, t->reps, 0, t->io, t->has_lines ? 1 : 0);
         HIP_TRY(hipGetLastError());
         if ((st = d2h(t, &io, t->io, sizeof(io)))) return st;
         if (io.status != -7) break;
@@ -831,6 +826,7 @@ static int rounds_of(const bhmc_tree* t) {
 
 static void launch_mc(bhmc_tree* t, hipStream_t s, bhmc::McArgs a, int grid, int wide) {
     const int bm = rounds_of(t);
+    a.lines = t->has_lines ? 1 : 0;
     if (bm <= 1) {
         t->ops->mc(s, t->reps, a, grid, wide);
     } else {

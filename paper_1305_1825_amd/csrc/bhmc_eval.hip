@@ -907,6 +907,7 @@ __device__ __forceinline__ double walk_value(const Rep& R, double4 sc, double x,
 
 // ------------------------------------------------------------ one Monte Carlo move
 constexpr int kMaxPathCells = 4 * kMaxLevels;
+constexpr int kLineContrib = 16;  // old and new position of up to 8 line images of the mover
 constexpr int kPowCells = 24;  // longer path-cell lists build their monomials by repeated products
 constexpr int kDrawBatch = 64;  // trial moves drawn ahead at once, one per lane of the first wave
 
@@ -942,6 +943,18 @@ struct McShared {
     // powers 0..p of each contribution's offset from each of the first kPowCells list cells,
     // per axis: d^n = x^n1 y^n2 z^n3 by two products
     double pw[kPowCells][4][3][P + 1];
+    // the mover's line images (multiple-image model): old (2m) and new (2m + 1) position and
+    // charge of line image m, the root paths of both, descended beside the traversal; for each
+    // old one and each target the first path cell passing the MAC (level, or -1: its leaf sums
+    // it directly; and its geometry); each new leaf's count and capacity
+    double4 lpos[kLineContrib];
+    double4 lmac_geo[kLineContrib / 2][2];
+    uint64_t lkey[kLineContrib];
+    int lpath[kLineContrib][kMaxLevels];
+    int lplen[kLineContrib];
+    int lmac[kLineContrib / 2][2];
+    int lcnt[kLineContrib / 2], lcap[kLineContrib / 2];
+    int lnext[kLineContrib];  // next level of each line path; -1 before its position is read
 };
 
 struct MoveOut { double dE; int reason; int accepted; int stop; int detail; };
@@ -973,188 +986,233 @@ __device__ __forceinline__ void prefetch_stage(const Rep& R, McShared& MS, int j
 // ------------------------------------------------------------ line images of the mover
 // The multiple-image model gives each ion M line-image sources (2n + m n + i) besides
 // its Kelvin image.  A move keeps the mover's own line images in its traversal as
-// ordinary sources and takes each back out of both potentials where the traversal met
-// it (lines_correct); an accepted move then checks every leaf it fills (lines_prepare)
-// and moves the line images after the ion and its image, in source order, as the
-// local modification of Sec. 3.3 (lines_commit).  The work arrays sit in the frontier
-// buffer, which the traversal no longer needs by then.
-constexpr int kLineContrib = 16;  // old and new position of up to 8 line images
-struct LineWork {
-    double px[kLineContrib], py[kLineContrib], pz[kLineContrib], pq[kLineContrib];  // 2m: old, 2m + 1: new
-    double corr[2];                              // per target: what the mover's line images added
-    int path[kLineContrib][kMaxLevels];          // root path of each contribution
-    int plen[kLineContrib];
-    int cnt[8], cap[8];                          // count and capacity of each new leaf
-    int ok, nlist;
-    int list_cell[kLineContrib * kMaxLevels];    // distinct path cells
-    uint32_t list_mask[kLineContrib * kMaxLevels];  // bit j: contribution j applies; bit 16: internal cell
+// ordinary sources.  Beside the traversal, lanes of an otherwise idle wave descend the
+// root paths of their old and new positions (line_step), noting for each old one the
+// first cell that passes the MAC for each target; afterwards each is taken back out of
+// both potentials where the traversal met it (line_corrections), every leaf an accepted
+// move fills is checked in commit order, and the line images are moved after the ion and
+// its image, in source order, by the local modification of Sec. 3.3 (lines_commit).
+
+// One step of line contribution j's root path (j = 2m: old position of line image m,
+// 2m + 1: new), as the ion's own paths descend.
+__device__ __forceinline__ void line_step(const Rep& R, McShared& MS, const double* tx, const double* ty,
+                                          const double* tz, int j, int level, int i) {
+    const int c = MS.lpath[j][level];
+    const bool cok = c >= 0 && c < R.ncell;
+    const bool old = (j & 1) == 0;
+    int4 m = make_int4(0, -1, 0, 0);
+    double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (cok) {
+        m = gload(R.cm + c);
+        if (old) g = gload(R.cgeo + c);
+    }
+    if (!cok || (m.y >= 0 && m.y + 8 > R.ncell)) {
+        MS.err = kErrPathCell;
+        MS.lplen[j] = level + 1;
+        MS.lpath[j][level] = 0;
+        return;
+    }
+    if (old) {
+        const int mm = j >> 1;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (MS.lmac[mm][t] >= 0) continue;
+            const double dx = g.x - tx[t], dy = g.y - ty[t], dz = g.z - tz[t];
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (3.0 * (g.w * g.w) <= R.theta2 * d2) { MS.lmac[mm][t] = level; MS.lmac_geo[mm][t] = g; }
+        }
+    }
+    if (m.y >= 0 && level + 1 < kMaxLevels) {
+        MS.lpath[j][level + 1] = m.y + key_digit(MS.lkey[j], level + 1);
+        return;
+    }
+    if (m.y >= 0) MS.err = kErrPathDepth;
+    MS.lplen[j] = level + 1;
+    if (!old) {
+        MS.lcnt[j >> 1] = m.x;
+        MS.lcap[j >> 1] = m.w;
+        if (m.z < 0 || m.x < 0 || m.z + m.w > R.pool) MS.err = kErrCommitLeaf;
+    } else if (gload(R.track + (2 * R.n + (j >> 1) * R.n + i)).x != c) {
+        MS.err = kErrCommitSlot;  // the tracked leaf must be the one the old position's key leads to
+    }
+}
+
+// Up to nsteps steps of line contribution j = tl's root path, its position read (old) or
+// placed as the build places it from the new Kelvin image (new) on the first call.  The
+// lane's state lives in LDS, so nothing of it stays in registers across the traversal.
+__device__ __attribute__((noinline)) void line_lane_steps(const Rep& R, McShared& MS, const double* tx,
+                                                          const double* ty, const double* tz, int tl, int i,
+                                                          int nsteps) {
+    int level = MS.lnext[tl];
+    if (level < 0) {
+        const int m = tl >> 1;
+        double4 p;
+        if (tl & 1) {
+            const double4 k = MS.contrib[3];
+            p = make_double4(R.line_t[m] * k.x, R.line_t[m] * k.y, R.line_t[m] * k.z, R.line_c[m] * k.w);
+        } else {
+            p = gload(R.src + (2 * R.n + m * R.n + i));
+        }
+        MS.lpos[tl] = p;
+        MS.lkey[tl] = morton_key(R, p.x, p.y, p.z);
+        level = 0;
+    }
+    for (int k = 0; k < nsteps && MS.lplen[tl] == 0 && level < kMaxLevels; ++k) line_step(R, MS, tx, ty, tz, tl, level++, i);
+    MS.lnext[tl] = level;
+}
+
+// What the mover's own line images added to the potential at target t, from the paths
+// descended beside the traversal: line image m through the expansion of the first cell of
+// its root path that passes the MAC, else directly at its leaf.  Lanes 2m + t of every
+// wave compute it, so each wave holds the sums without a barrier.
+__device__ __attribute__((noinline)) void line_corrections(const Rep& R, const McShared& MS, double& c0, double& c1) {
+    const int lane = lane_id(), t = lane & 1, m = lane >> 1;
+    double v = 0.0;
+    if (m < R.nline) {
+        const double4 sc = MS.lpos[2 * m], x = MS.contrib[t];
+        const int l = MS.lmac[m][t];
+        if (l >= 0) {
+            const double4 g = MS.lmac_geo[m][t];
+            v = sc.w * point_expansion(g.x - x.x, g.y - x.y, g.z - x.z, sc.x - g.x, sc.y - g.y, sc.z - g.z);
+        } else {
+            const double ex = x.x - sc.x, ey = x.y - sc.y, ez = x.z - sc.z;
+            v = sc.w * rsqrt_nr(ex * ex + ey * ey + ez * ez);
+        }
+    }
+    c0 = wave_sum(t == 0 ? v : 0.0);
+    c1 = wave_sum(t == 1 ? v : 0.0);
+}
+
+// Would the 2 + M insertions of this move (ion, Kelvin image, line images in source
+// order) overflow a leaf?  Each new leaf is checked with the counts the earlier ones
+// leave behind.
+__device__ __forceinline__ int fit_old_leaf(const McShared& MS, int k) {
+    return k == 0 ? MS.tr[0].x : (k == 1 ? MS.tr[1].x : MS.lpath[2 * (k - 2)][MS.lplen[2 * (k - 2)] - 1]);
+}
+__device__ __forceinline__ int fit_new_leaf(const McShared& MS, int k) {
+    return k < 2 ? MS.path[2 * k + 1][MS.plen[2 * k + 1] - 1] : MS.lpath[2 * (k - 2) + 1][MS.lplen[2 * (k - 2) + 1] - 1];
+}
+__device__ __attribute__((noinline)) bool lines_fit(const Rep& R, const McShared& MS) {
+    for (int k = 0; k < 2 + R.nline; ++k) {
+        const int lo = fit_old_leaf(MS, k), ln = fit_new_leaf(MS, k);
+        if (ln == lo) continue;
+        int c = k < 2 ? MS.lm_new[k].x : MS.lcnt[k - 2];
+        const int cap = k < 2 ? MS.lm_new[k].w : MS.lcap[k - 2];
+        for (int e = 0; e < k; ++e) {
+            const int eo = fit_old_leaf(MS, e), en = fit_new_leaf(MS, e);
+            if (en == eo) continue;
+            if (en == ln) c += 1;
+            if (eo == ln) c -= 1;
+        }
+        if (c + 1 > cap) return false;
+    }
+    return true;
+}
+
+// Distinct cells of the 2M line paths, built in the frontier buffer (free after the
+// traversal): bit j of a cell's mask = contribution j applies; kLineInternal = not a leaf.
+struct LineList {
+    int nlist;
+    int cell[kLineContrib * kMaxLevels];
+    uint32_t mask[kLineContrib * kMaxLevels];
 };
 constexpr uint32_t kLineInternal = 1u << 16;
 
 template <int BLOCK>
-__device__ __forceinline__ LineWork& line_work(Trav<2, BLOCK>& S) {
-    static_assert(sizeof(LineWork) <= sizeof(S.front), "the line-image work arrays must fit the frontier buffer");
-    return *reinterpret_cast<LineWork*>(&S.front[0][0]);
+__device__ __forceinline__ LineList& line_list(Trav<2, BLOCK>& S) {
+    static_assert(sizeof(LineList) <= sizeof(S.front), "the line-path cell list must fit the frontier buffer");
+    return *reinterpret_cast<LineList*>(&S.front[0][0]);
 }
 
-// Lanes 2m and 2m + 1 of the first wave walk line image m's root path from the old and
-// the new position of the mover; LW.corr[t] receives the sum over m.
-template <int BLOCK>
-__device__ __forceinline__ void lines_correct(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i) {
-    LineWork& LW = line_work(S);
-    if (wave_id() == 0) {
-        const int lane = lane_id(), t = lane & 1, m = lane >> 1;
-        double v = 0.0;
-        if (m < R.nline) {
-            const double4 x = MS.contrib[t];
-            const double4 sc = R.src[2 * R.n + m * R.n + i];
-            int bad = 0;
-            v = sc.w * walk_value(R, sc, x.x, x.y, x.z, bad);
-            if (bad) MS.err = kErrPathCell;
+// Move one line image between leaf index arrays (or rewrite its slot) from the current
+// state in HBM; false on a broken index.
+__device__ __forceinline__ bool line_slot_move(const Rep& R, int s, int lo, int ln, double4 pn) {
+    const int2 tr = R.track[s];
+    const int4 mo = R.cm[lo];
+    if (tr.x != lo || mo.y >= 0 || tr.y < 0 || tr.y >= mo.x || mo.z < 0 || mo.z + mo.x > R.pool) return false;
+    if (ln != lo) {
+        const int last = mo.x - 1, k = tr.y;
+        const int4 mn = R.cm[ln];
+        if (mn.y >= 0 || mn.x < 0 || mn.x + 1 > mn.w || mn.z < 0 || mn.z + mn.w > R.pool) return false;
+        if (k != last) {
+            const int moved = R.pidx[mo.z + last];
+            if (moved < 0 || moved >= R.nsrc) return false;
+            R.pool4[mo.z + k] = R.pool4[mo.z + last];
+            R.pidx[mo.z + k] = moved;
+            R.track[moved] = make_int2(lo, k);
         }
-        const double c0 = wave_sum(t == 0 ? v : 0.0), c1 = wave_sum(t == 1 ? v : 0.0);
-        if (lane == 0) { LW.corr[0] = c0; LW.corr[1] = c1; }
+        R.cm[lo].x = last;
+        R.pool4[mn.z + mn.x] = pn;
+        R.pidx[mn.z + mn.x] = s;
+        R.track[s] = make_int2(ln, mn.x);
+        R.cm[ln].x = mn.x + 1;
+    } else {
+        R.pool4[mo.z + tr.y] = pn;
     }
-    __syncthreads();
+    R.src[s] = pn;
+    return true;
 }
 
-// Root paths of the old and new line images (thread 2m + k, k = 1 for the new one), then
-// on one thread the capacity check of all 2 + M moved sources in commit order: each one's
-// new leaf with the counts the earlier ones leave behind.
-template <int BLOCK>
-__device__ __forceinline__ void lines_prepare(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i) {
-    LineWork& LW = line_work(S);
-    const int tid = threadIdx.x, M = R.nline;
-    if (tid < 2 * M) {
-        const int m = tid >> 1, isnew = tid & 1, s = 2 * R.n + m * R.n + i;
-        double4 p;
-        if (isnew) {  // placed as the build places it, from the new Kelvin image
-            const double4 k = MS.contrib[3];
-            p = make_double4(R.line_t[m] * k.x, R.line_t[m] * k.y, R.line_t[m] * k.z, R.line_c[m] * k.w);
-        } else {
-            p = R.src[s];
-        }
-        LW.px[tid] = p.x; LW.py[tid] = p.y; LW.pz[tid] = p.z; LW.pq[tid] = p.w;
-        const uint64_t key = morton_key(R, p.x, p.y, p.z);
-        int c = 0, len = 0;
-        bool leaf = false;
-        for (int level = 0; level < kMaxLevels; ++level) {
-            if (c < 0 || c >= R.ncell) break;
-            LW.path[tid][level] = c;
-            len = level + 1;
-            const int4 cm = R.cm[c];
-            if (cm.y < 0) {
-                leaf = true;
-                if (isnew) { LW.cnt[m] = cm.x; LW.cap[m] = cm.w; }
-                break;
-            }
-            if (cm.y + 8 > R.ncell) break;
-            c = cm.y + key_digit(key, level + 1);
-        }
-        if (!leaf) { MS.err = kErrPathCell; len = 1; LW.path[tid][0] = 0; }
-        LW.plen[tid] = len;
-        if (leaf && !isnew && R.track[s].x != c) MS.err = kErrCommitSlot;  // the tracked leaf must be this one
-    }
-    __syncthreads();
-    if (tid == 0 && !MS.err) {
-        int lo[2 + 8], ln[2 + 8], cnt[2 + 8], cap[2 + 8];
-        lo[0] = MS.tr[0].x; ln[0] = MS.path[1][MS.plen[1] - 1]; cnt[0] = MS.lm_new[0].x; cap[0] = MS.lm_new[0].w;
-        lo[1] = MS.tr[1].x; ln[1] = MS.path[3][MS.plen[3] - 1]; cnt[1] = MS.lm_new[1].x; cap[1] = MS.lm_new[1].w;
-        for (int m = 0; m < M; ++m) {
-            lo[2 + m] = LW.path[2 * m][LW.plen[2 * m] - 1];
-            ln[2 + m] = LW.path[2 * m + 1][LW.plen[2 * m + 1] - 1];
-            cnt[2 + m] = LW.cnt[m]; cap[2 + m] = LW.cap[m];
-        }
-        bool ok = true;
-        for (int k = 0; k < 2 + M; ++k) {
-            if (ln[k] == lo[k]) continue;
-            int c = cnt[k];
-            for (int e = 0; e < k; ++e) {
-                if (ln[e] == lo[e]) continue;
-                if (ln[e] == ln[k]) c += 1;
-                if (lo[e] == ln[k]) c -= 1;
-            }
-            if (c + 1 > cap[k]) ok = false;
-        }
-        LW.ok = ok;
-    }
-    __syncthreads();
-}
-
-// After the ion and its image: thread 0 moves the line images between leaf index arrays
-// in source order (delete = the last entry fills the hole; add = append), then every
-// thread repairs the moments and counts of the distinct cells of their 2M root paths,
+// After the ion and its image: the line images' slot moves (one lane each when no two
+// of them touch a common leaf, else one lane in source order), beside them the distinct
+// cells of their 2M root paths, then every thread repairs those cells' moments and counts,
 // applying to each cell, in order, old line image 0 (-), new line image 0 (+), old 1 ...
+// LL.nlist must be 0 on entry.
 template <int BLOCK>
 __device__ __forceinline__ void lines_commit(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i) {
-    LineWork& LW = line_work(S);
+    LineList& LL = line_list(S);
     const int tid = threadIdx.x, M = R.nline, nc = 2 * M;
-    if (tid == 0) {
-        for (int m = 0; m < M; ++m) {
-            const int s = 2 * R.n + m * R.n + i;
-            const int lo = LW.path[2 * m][LW.plen[2 * m] - 1], ln = LW.path[2 * m + 1][LW.plen[2 * m + 1] - 1];
-            const double4 pn = make_double4(LW.px[2 * m + 1], LW.py[2 * m + 1], LW.pz[2 * m + 1], LW.pq[2 * m + 1]);
-            const int2 tr = R.track[s];
-            const int4 mo = R.cm[lo];
-            if (tr.x != lo || mo.y >= 0 || tr.y < 0 || tr.y >= mo.x || mo.z < 0 || mo.z + mo.x > R.pool) {
-                MS.err = kErrCommitSlot;
-                break;
-            }
-            if (ln != lo) {
-                const int last = mo.x - 1, k = tr.y;
-                if (k != last) {
-                    const int moved = R.pidx[mo.z + last];
-                    if (moved < 0 || moved >= R.nsrc) { MS.err = kErrCommitSource; break; }
-                    R.pool4[mo.z + k] = R.pool4[mo.z + last];
-                    R.pidx[mo.z + k] = moved;
-                    R.track[moved] = make_int2(lo, k);
-                }
-                R.cm[lo].x = last;
-                const int4 mn = R.cm[ln];
-                if (mn.y >= 0 || mn.x < 0 || mn.x + 1 > mn.w || mn.z < 0 || mn.z + mn.w > R.pool) {
-                    MS.err = kErrCommitLeaf;
-                    break;
-                }
-                R.pool4[mn.z + mn.x] = pn;
-                R.pidx[mn.z + mn.x] = s;
-                R.track[s] = make_int2(ln, mn.x);
-                R.cm[ln].x = mn.x + 1;
-            } else {
-                R.pool4[mo.z + tr.y] = pn;
-            }
-            R.src[s] = pn;
+    if (wave_id() == 0) {
+        const int m = lane_id();
+        int lo = -1, ln = -1;
+        if (m < M) {
+            lo = MS.lpath[2 * m][MS.lplen[2 * m] - 1];
+            ln = MS.lpath[2 * m + 1][MS.lplen[2 * m + 1] - 1];
         }
-        LW.nlist = 0;
+        bool clash = false;
+        for (int e = 0; e < M; ++e) {
+            const int eo = __shfl(lo, e, 64), en = __shfl(ln, e, 64);
+            if (m < M && e != m && (eo == lo || eo == ln || en == lo || en == ln)) clash = true;
+        }
+        if (__ballot(clash) == 0) {
+            if (m < M && !line_slot_move(R, 2 * R.n + m * R.n + i, lo, ln, MS.lpos[2 * m + 1])) MS.err = kErrCommitSlot;
+        } else if (m == 0) {
+            for (int k = 0; k < M; ++k) {
+                const int ko = MS.lpath[2 * k][MS.lplen[2 * k] - 1], kn = MS.lpath[2 * k + 1][MS.lplen[2 * k + 1] - 1];
+                if (!line_slot_move(R, 2 * R.n + k * R.n + i, ko, kn, MS.lpos[2 * k + 1])) { MS.err = kErrCommitSlot; break; }
+            }
+        }
+    } else {
+        for (int it = tid - 64; it < nc * kMaxLevels; it += BLOCK - 64) {
+            const int j = it / kMaxLevels, l = it % kMaxLevels;
+            if (l >= MS.lplen[j]) continue;
+            const int c = MS.lpath[j][l];
+            bool owner = true;
+            for (int jj = 0; jj < j; ++jj)
+                if (l < MS.lplen[jj] && MS.lpath[jj][l] == c) owner = false;
+            if (!owner) continue;
+            uint32_t mask = l < MS.lplen[j] - 1 ? kLineInternal : 0u;
+            for (int jj = j; jj < nc; ++jj)
+                if (l < MS.lplen[jj] && MS.lpath[jj][l] == c) mask |= 1u << jj;
+            const int slot = atomicAdd(&LL.nlist, 1);
+            LL.cell[slot] = c;
+            LL.mask[slot] = mask;
+        }
     }
     __syncthreads();
-    for (int it = tid; it < nc * kMaxLevels; it += BLOCK) {
-        const int j = it / kMaxLevels, l = it % kMaxLevels;
-        if (l >= LW.plen[j]) continue;
-        const int c = LW.path[j][l];
-        bool owner = true;
-        for (int jj = 0; jj < j; ++jj)
-            if (l < LW.plen[jj] && LW.path[jj][l] == c) owner = false;
-        if (!owner) continue;
-        uint32_t mask = l < LW.plen[j] - 1 ? kLineInternal : 0u;
-        for (int jj = j; jj < nc; ++jj)
-            if (l < LW.plen[jj] && LW.path[jj][l] == c) mask |= 1u << jj;
-        const int slot = atomicAdd(&LW.nlist, 1);
-        LW.list_cell[slot] = c;
-        LW.list_mask[slot] = mask;
-    }
-    __syncthreads();
-    const int items = LW.nlist * NTERM;
+    const int items = LL.nlist * NTERM;
     for (int it = tid; it < items; it += BLOCK) {
         const int li = it / NTERM, k = it % NTERM;
-        const int c = LW.list_cell[li];
-        const uint32_t mask = LW.list_mask[li];
+        const int c = LL.cell[li];
+        const uint32_t mask = LL.mask[li];
         const double4 g = R.cgeo[c];
         double mk = R.M[(size_t)c * MSTR + k];
         int dc = 0;
         for (int j = 0; j < nc; ++j) {
             if (!(mask & (1u << j))) continue;
-            const double v = mono(S.mi[k], LW.px[j] - g.x, LW.py[j] - g.y, LW.pz[j] - g.z);
-            if (j & 1) { mk = mk + LW.pq[j] * v; ++dc; } else { mk = mk - LW.pq[j] * v; --dc; }
+            const double4 sp = MS.lpos[j];
+            const double v = mono(S.mi[k], sp.x - g.x, sp.y - g.y, sp.z - g.z);
+            if (j & 1) { mk = mk + sp.w * v; ++dc; } else { mk = mk - sp.w * v; --dc; }
         }
         R.M[(size_t)c * MSTR + k] = mk;
         if (R.M32) R.M32[(size_t)c * MSTR + k] = (float)mk;
@@ -1309,7 +1367,7 @@ __device__ __forceinline__ void commit(const Rep& R, const Trav<2, BLOCK>& S, Mc
 // si and mo are the mover's ion and image as stored (mo unused without images);
 // inext >= 0 names the next move's ion, whose sources one lane loads into
 // MS.nx_si / MS.nx_mo during the traversal (valid if the ion is not i).
-template <int BLOCK>
+template <int BLOCK, bool LINES>
 __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McShared& MS, int i, double4 si,
                             double4 mo, double rx, double ry, double rz, double alpha, int mode, int inext) {
     static_assert(BLOCK >= 256, "the path descents, the commit prefetch and the next mover's load run on "
@@ -1377,6 +1435,17 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     if (th >= 0 && th < 4) { MS.path[th][0] = 0; MS.plen[th] = 0; }
     if (tp == 0 || tp == 1) MS.pf_stage[tp] = (tp == 1 && !imgs) ? 3 : 0;
     int my_level = 0;  // the next level of this lane's root path
+    // the line images' root paths (multiple-image model) on lanes 16 .. 16 + 2M - 1 of the
+    // wave that loads the next mover
+    {
+        const int tl = tid - (BLOCK - 192) - 16;
+        if (LINES && tl >= 0 && tl < 2 * R.nline) {
+            MS.lpath[tl][0] = 0;
+            MS.lplen[tl] = 0;
+            MS.lnext[tl] = -1;
+            if (!(tl & 1)) { MS.lmac[tl >> 1][0] = -1; MS.lmac[tl >> 1][1] = -1; }
+        }
+    }
     __syncthreads();
     // one step of a root path: descend by the key's digit, or stop at the leaf
     auto step = [&](int pj, int level) {
@@ -1411,6 +1480,8 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
             MS.nx_si = R.src[inext];
             MS.nx_mo = imgs ? R.src[R.n + inext] : make_double4(0, 0, 0, 0);
         }
+        if (LINES && tid - (BLOCK - 192) - 16 >= 0 && tid - (BLOCK - 192) - 16 < 2 * R.nline)
+            line_lane_steps(R, MS, S.tx, S.ty, S.tz, tid - (BLOCK - 192) - 16, i, 2);
     };
     double pot[2];
     const int levels = traverse_mc<BLOCK>(R, S, MS.cnt2, hook, MS.fs0, MS.level0, pot);
@@ -1429,6 +1500,13 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         const int s = tp == 0 ? i : R.n + i;
         for (int k = 0; k < 3 && MS.pf_stage[tp] < 3; ++k) prefetch_stage(R, MS, tp, s);
         if (MS.pf_stage[tp] != 3) MS.err = kErrCommitSlot;
+    }
+    {
+        const int tl = tid - (BLOCK - 192) - 16;
+        if (LINES && tl >= 0 && tl < 2 * R.nline) {
+            line_lane_steps(R, MS, S.tx, S.ty, S.tz, tl, i, kMaxLevels);
+            if (MS.lplen[tl] == 0) { MS.err = kErrPathDepth; MS.lplen[tl] = 1; MS.lpath[tl][0] = 0; }
+        }
     }
     __syncthreads();
     if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
@@ -1452,24 +1530,20 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     const double po = pot[0], pn = pot[1];
     if (S.overlap || S.coincide) { out.reason = 2; __syncthreads(); return out; }
     double lc0 = 0.0, lc1 = 0.0;  // what the mover's own line images added at the two targets
-    if (R.nline > 0) {
-        lines_correct<BLOCK>(R, S, MS, i);
-        if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
-        lc0 = line_work(S).corr[0];
-        lc1 = line_work(S).corr[1];
-    }
+    if (LINES && R.nline > 0) line_corrections(R, MS, lc0, lc1);
     // the move's positions and alpha come back from LDS: no registers held across the traversal
     const double4 so = MS.contrib[0], sn = MS.contrib[1];
     const double q = so.w, l = R.l_B;
-    double dE = R.nline > 0 ? l * q * ((pn - lc1) - (po - lc0)) : l * q * (pn - po);
+    double dE = LINES && R.nline > 0 ? l * q * ((pn - lc1) - (po - lc0)) : l * q * (pn - po);
     if (R.geom == 1) {
         const double rn2 = sn.x * sn.x + sn.y * sn.y + sn.z * sn.z;
         const double ro2 = so.x * so.x + so.y * so.y + so.z * so.z;
         if (imgs) dE += 0.5 * l * R.gamma * R.a * q * q * (1.0 / (rn2 - R.a2) - 1.0 / (ro2 - R.a2));
         // own line images: c_m q_K at t_m r_K, |r - t_m r_K| = (r^2 - t_m a^2) / |r|
-        for (int m = 0; m < R.nline; ++m)
-            dE += 0.5 * l * R.line_c[m] * R.gamma * R.a * q * q *
-                  (1.0 / (rn2 - R.line_t[m] * R.a2) - 1.0 / (ro2 - R.line_t[m] * R.a2));
+        if (LINES)
+            for (int m = 0; m < R.nline; ++m)
+                dE += 0.5 * l * R.line_c[m] * R.gamma * R.a * q * q *
+                      (1.0 / (rn2 - R.line_t[m] * R.a2) - 1.0 / (ro2 - R.line_t[m] * R.a2));
         if (R.Qc != 0.0) dE += l * R.Qc * q * (1.0 / sqrt(rn2) - 1.0 / sqrt(ro2));
     }
     out.dE = dE;
@@ -1477,7 +1551,6 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
     if (mode == 1) acc = dE <= 0.0 || MS.alpha <= exp(-dE);
     else if (mode == 2) acc = true;
     if (!acc) { __syncthreads(); return out; }
-    if (R.nline > 0) lines_prepare<BLOCK>(R, S, MS, i);
     if (tid == BLOCK - 1) {  // a thread with no path-cell item above
         // the tracked leaves must be the leaves the old positions' keys lead to,
         // and the tracked slots must hold the movers
@@ -1499,14 +1572,17 @@ __device__ __forceinline__ MoveOut one_move(const Rep& R, Trav<2, BLOCK>& S, McS
         } else {
             MS.err = kErrCommitSlot;
         }
-        if (R.nline > 0 && !line_work(S).ok) ok = false;  // the line images' leaves, checked in order
+        if (LINES && R.nline > 0) {
+            if (ok && !lines_fit(R, MS)) ok = false;  // every insertion of the move, in commit order
+            line_list(S).nlist = 0;
+        }
         MS.ok = ok;
     }
     __syncthreads();
     if (MS.err) { out.stop = -8; out.detail = MS.err; __syncthreads(); return out; }
     if (!MS.ok) { out.stop = -6; __syncthreads(); return out; }
     commit<BLOCK>(R, S, MS, i);
-    if (R.nline > 0 && !MS.err) lines_commit<BLOCK>(R, S, MS, i);
+    if (LINES && R.nline > 0 && !MS.err) lines_commit<BLOCK>(R, S, MS, i);
     if (MS.err) { out.stop = -8; out.detail = MS.err; }
     out.accepted = 1;
     return out;
@@ -1531,7 +1607,7 @@ __device__ __forceinline__ void load_rep(Rep& dst, const Rep* src) {
 // treecode energy change and the local adjustment of Sec. 3.3).  A replica
 // whose accepted move would overflow a leaf index array stops before that
 // move with mc_status = ECAPACITY; the host rebuilds it and resumes.
-template <int BLOCK>
+template <int BLOCK, bool LINES>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_mc(Rep* reps, McArgs A) {
     __shared__ Trav<2, BLOCK> S;
     __shared__ McShared MS;
@@ -1574,7 +1650,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
             const bool use_nx = have_nx && i != prev_i;
             const double4 si = use_nx ? MS.nx_si : Rs.src[i];
             const double4 mo = use_nx ? MS.nx_mo : (imgs ? Rs.src[Rs.n + i] : make_double4(0, 0, 0, 0));
-            const MoveOut o = one_move<BLOCK>(Rs, S, MS, i, si, mo, si.x + MS.dr_d[b][0], si.y + MS.dr_d[b][1],
+            const MoveOut o = one_move<BLOCK, LINES>(Rs, S, MS, i, si, mo, si.x + MS.dr_d[b][0], si.y + MS.dr_d[b][1],
                                               si.z + MS.dr_d[b][2], MS.dr_d[b][3], 1, inext);
             // a move outside the walls returns before its traversal, so before the load
             have_nx = inext >= 0 && o.reason != 1;
@@ -1600,6 +1676,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
     }
 }
 
+template <bool LINES>
 __global__ void __launch_bounds__(kMcBlock) k_move(Rep* reps, int r, MoveIO* io) {
     __shared__ Trav<2, kMcBlock> S;
     __shared__ McShared MS;
@@ -1610,7 +1687,7 @@ __global__ void __launch_bounds__(kMcBlock) k_move(Rep* reps, int r, MoveIO* io)
     const int i = io->i;
     const double4 si = Rs.src[i];
     const double4 mo = Rs.images ? Rs.src[Rs.n + i] : make_double4(0, 0, 0, 0);
-    const MoveOut o = one_move<kMcBlock>(Rs, S, MS, i, si, mo, io->rn[0], io->rn[1], io->rn[2], 0.0,
+    const MoveOut o = one_move<kMcBlock, LINES>(Rs, S, MS, i, si, mo, io->rn[0], io->rn[1], io->rn[2], 0.0,
                                          io->mode == 0 ? 0 : 2, -1);
     if (threadIdx.x == 0) {
         io->dE = o.dE;
@@ -2117,6 +2194,73 @@ __global__ void __launch_bounds__(256) k_gflag(Rep* reps, int r, const int* fcel
     G[R.n + ion] = gs;
 }
 
+// The target's own line images (multiple-image model; one thread per ion, after
+// k_gflag): k_grad kept them in the ion's traversal as ordinary sources, so each pair
+// term of the ion with one of them comes back out where the traversal met it -- through
+// the expansion of the first cell of the line image's root path that passes the MAC,
+// else directly at its leaf -- from the ion's potential, field and energy term and from
+// the line image's source-side gradient.  The ion's energy with its own line images,
+// 1/2 q sum_m c_m q_K / |r - t_m r_K|, joins its energy term (its gradient is k_chain's).
+__global__ void __launch_bounds__(256) k_gline(Rep* reps, int r, double4* G, double4* Gt, double* eterm) {
+    const Rep& R = reps[r];
+    const int ion = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ion >= R.n || R.nline <= 0) return;
+    const double4 x = R.src[ion];
+    const double half_lB = 0.5 * R.l_B, wq = half_lB * x.w;
+    double4 gt = Gt[ion];
+    double e = eterm[ion];
+    for (int m = 0; m < R.nline; ++m) {
+        const int s = 2 * R.n + m * R.n + ion;
+        const double4 y = R.src[s];
+        const uint64_t key = morton_key(R, y.x, y.y, y.z);
+        int c = 0, far = -1;
+        bool leaf = false;
+        double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
+        for (int level = 0; level < kMaxLevels; ++level) {
+            if (c < 0 || c >= R.ncell) break;
+            g = R.cgeo[c];
+            const double dx = g.x - x.x, dy = g.y - x.y, dz = g.z - x.z;
+            if (3.0 * (g.w * g.w) <= R.theta2 * (dx * dx + dy * dy + dz * dz)) { far = c; break; }
+            const int link = R.cm[c].y;
+            if (link < 0) { leaf = true; break; }
+            if (link + 8 > R.ncell) break;
+            c = link + key_digit(key, level + 1);
+        }
+        double v, F[3] = {0.0, 0.0, 0.0}, Gk[3] = {0.0, 0.0, 0.0};
+        if (far >= 0) {
+            const double Rx = g.x - x.x, Ry = g.y - x.y, Rz = g.z - x.z;
+            double T[NTERM1], D[NTERM];
+            T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
+            v = 0.0;
+            flag_rec<0>(T, D, Rx, Ry, Rz, T[0] * T[0], y.x - g.x, y.y - g.y, y.z - g.z, v, F, Gk);
+        } else if (leaf) {
+            // 1/|x - y|: -d/dx = d/dy = (x - y) / |x - y|^3
+            const double ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
+            const double ir = rsqrt_nr(ex * ex + ey * ey + ez * ez), ir3 = ir * ir * ir;
+            v = ir;
+            F[0] = Gk[0] = ex * ir3; F[1] = Gk[1] = ey * ir3; F[2] = Gk[2] = ez * ir3;
+        } else {
+            reps[r].err_detail = kErrPathCell;
+            v = __builtin_nan("");
+        }
+        gt.x += wq * (y.w * F[0]);
+        gt.y += wq * (y.w * F[1]);
+        gt.z += wq * (y.w * F[2]);
+        gt.w -= half_lB * (y.w * v);
+        e -= 0.5 * x.w * (y.w * v);
+        double4 gs = G[s];
+        gs.x -= wq * y.w * Gk[0];
+        gs.y -= wq * y.w * Gk[1];
+        gs.z -= wq * y.w * Gk[2];
+        gs.w -= wq * v;
+        G[s] = gs;
+    }
+    const double r2 = x.x * x.x + x.y * x.y + x.z * x.z;
+    for (int m = 0; m < R.nline; ++m) e += 0.5 * x.w * (R.line_c[m] * R.gamma * R.a * x.w / (r2 - R.line_t[m] * R.a2));
+    Gt[ion] = gt;
+    eterm[ion] = e;
+}
+
 // Ion groups of the gradient traversal: the ions in the order of the build's
 // key sort (a space-filling curve, so consecutive ions are close in space).
 // rank[k] counts the ions before sorted position k; islot[rank] is the
@@ -2197,7 +2341,13 @@ __global__ void __launch_bounds__(256) k_chain(const Rep* reps, int r, const dou
     const double l = R.l_B;
     const double r2 = x * x + y * y + z * z;
     if (R.images) {
-        const double4 h = G[R.n + i];
+        // a line image sits at t_m r_K with charge c_m q_K: its gradient joins the Kelvin image's
+        double4 h = G[R.n + i];
+        for (int m = 0; m < R.nline; ++m) {
+            const double4 hm = G[2 * R.n + m * R.n + i];
+            h.x += R.line_t[m] * hm.x; h.y += R.line_t[m] * hm.y; h.z += R.line_t[m] * hm.z;
+            h.w += R.line_c[m] * hm.w;
+        }
         const double rn = sqrt(r2);
         const double ir2 = 1.0 / r2, ir4 = ir2 * ir2;
         const double rh = x * h.x + y * h.y + z * h.z;
@@ -2211,6 +2361,13 @@ __global__ void __launch_bounds__(256) k_chain(const Rep* reps, int r, const dou
         const double cs = -l * R.gamma * R.a * q * q / (den * den);
         gx += cs * x; gy += cs * y; gz += cs * z;
         gq += l * R.gamma * R.a * q / den;
+        // the ion's energy with its own line images, 1/2 l_B c_m gamma a q^2 / (r^2 - t_m a^2)
+        for (int m = 0; m < R.nline; ++m) {
+            const double dm = r2 - R.line_t[m] * R.a2;
+            const double cl = -l * R.line_c[m] * R.gamma * R.a * q * q / (dm * dm);
+            gx += cl * x; gy += cl * y; gz += cl * z;
+            gq += l * R.line_c[m] * R.gamma * R.a * q / dm;
+        }
     }
     if (R.geom == 1 && R.Qc != 0.0) {
         const double rn = sqrt(r2);
@@ -2228,15 +2385,23 @@ __global__ void __launch_bounds__(256) k_zero(double* p, size_t n) {
 }
 
 void run_mc(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide) {
-    if (wide) hipLaunchKernelGGL(k_mc<kMcBlock>, dim3(grid), dim3(kMcBlock), 0, s, reps, a);
-    else hipLaunchKernelGGL(k_mc<kMcBlockBatch>, dim3(grid), dim3(kMcBlockBatch), 0, s, reps, a);
+    // handles with line images take the instantiation with their steps; the others keep the
+    // registers of the one-image kernel
+    if (a.lines) {
+        if (wide) hipLaunchKernelGGL((k_mc<kMcBlock, true>), dim3(grid), dim3(kMcBlock), 0, s, reps, a);
+        else hipLaunchKernelGGL((k_mc<kMcBlockBatch, true>), dim3(grid), dim3(kMcBlockBatch), 0, s, reps, a);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_mc<kMcBlock, false>), dim3(grid), dim3(kMcBlock), 0, s, reps, a);
+        else hipLaunchKernelGGL((k_mc<kMcBlockBatch, false>), dim3(grid), dim3(kMcBlockBatch), 0, s, reps, a);
+    }
 }
 void run_mcb(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide) {
     if (wide) hipLaunchKernelGGL(k_mcb<kMcBlock>, dim3(grid), dim3(kMcBlock), 0, s, reps, a);
     else hipLaunchKernelGGL(k_mcb<kMcBlockBatch>, dim3(grid), dim3(kMcBlockBatch), 0, s, reps, a);
 }
-void run_move(hipStream_t s, Rep* reps, int r, MoveIO* io) {
-    hipLaunchKernelGGL(k_move, dim3(1), dim3(kMcBlock), 0, s, reps, r, io);
+void run_move(hipStream_t s, Rep* reps, int r, MoveIO* io, int lines) {
+    if (lines) hipLaunchKernelGGL(k_move<true>, dim3(1), dim3(kMcBlock), 0, s, reps, r, io);
+    else hipLaunchKernelGGL(k_move<false>, dim3(1), dim3(kMcBlock), 0, s, reps, r, io);
 }
 // Line images of the multiple-image model (one thread per ion, after k_energy): an
 // ion's own line images stay in its traversal as sources, so each is taken back out of
@@ -2285,6 +2450,8 @@ void run_grad(hipStream_t s, Rep* reps, int r, const GradWork& w, double* dEdr, 
                        w.L, w.G, w.Gt, eterm, w.fcell);
     hipLaunchKernelGGL(k_gflag, dim3((w.n + 255) / 256), dim3(256), 0, s, reps, r, (const int*)w.fcell, w.G,
                        w.Gt, eterm);
+    if (w.nline > 0)
+        hipLaunchKernelGGL(k_gline, dim3((w.n + 255) / 256), dim3(256), 0, s, reps, r, w.G, w.Gt, eterm);
     hipLaunchKernelGGL(k_adj_down, dim3((w.nsrc + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,
                        (const double*)w.L, w.G);
     hipLaunchKernelGGL(k_chain, dim3((w.n + 255) / 256), dim3(256), 0, s, (const Rep*)reps, r,

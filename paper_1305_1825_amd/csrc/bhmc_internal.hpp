@@ -23,6 +23,7 @@ struct McArgs {
     long long move_base;  // move index of accept[0]
     long long* sweep_add; // per replica moves added to move_end by the sweep prep kernel
     int bm;               // batched kernel: moves per round (0 = as many as the order allows)
+    int lines;            // 1: a replica has line images (the move kernel with their steps)
 };
 
 // One externally specified move (delta_energy / commit_move).
@@ -56,6 +57,7 @@ struct GradWork {
     int* islot;           // per ion rank: its current slot (n)
     int* fcell;           // per ion: the far cell holding its own image in its traversal, or -1 (n)
     int ncell, nleaf, nsrc, n;
+    int nline;            // line images per ion (multiple-image model), 0 without
 };
 
 // ---- evaluation (bhmc_eval.hip, one translation unit per expansion order)
@@ -65,7 +67,7 @@ struct EvalOps {
     // the same chains with several trial moves per round (N_0 = 0 only)
     void (*mcb)(hipStream_t s, Rep* reps, const McArgs& a, int grid, int wide);
     int moves_per_round;  // the most the batched kernel takes per round at this order
-    void (*move)(hipStream_t s, Rep* reps, int r, MoveIO* io_dev);
+    void (*move)(hipStream_t s, Rep* reps, int r, MoveIO* io_dev, int lines);
     // max_grid > 0 bounds the number of workgroups (each then takes several target groups), so that
     // every workgroup has an HBM frontier region
     // nline > 0: the replica has line images (multiple-image model), corrected after the traversal
