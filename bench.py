@@ -44,11 +44,11 @@ GATED_REPLICAS = dict(theta=0.3, p=5, n0=0)
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
 # counters on a plain device copy), valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "csrc": "d378ab04d365",
-    "chain": {"units": 100000, "bytes": 183503242},        # eval_p5::k_mcb<512>, 10^5 moves
-    "sweep": {"units": 3038540, "bytes": 1.02692e12},      # eval_p5::k_mcb<512>, one sweep of 256 replicas
-    "sweep_fp32": {"units": 3038540, "bytes": 5.91956e11}, # the same with the single-precision far field
-    "grad": {"units": 1, "bytes": 1.15758e10},             # eval_p6::k_grad, one call at 10^5 ions
+    "csrc": "a074f91635f6",
+    "chain": {"units": 100000, "bytes": 184298609},        # eval_p5::k_mcb<512>, 10^5 moves
+    "sweep": {"units": 3038540, "bytes": 1.01363e12},      # eval_p5::k_mcb<512>, one sweep of 256 replicas
+    "sweep_fp32": {"units": 3038540, "bytes": 5.82627e11}, # the same with the single-precision far field
+    "grad": {"units": 1, "bytes": 1.15760e10},             # eval_p6::k_grad, one call at 10^5 ions
 }
 
 
@@ -74,7 +74,7 @@ def kernel_label(tune, p):
     or rounds of several (k_mcb), 512- or 256-thread workgroups."""
     mpr = tune.get("moves_per_round", 1)
     width = 512 if tune.get("shape_index", 0) == 0 else 256
-    name = "k_mc<%d>" % width if mpr == 1 else "k_mcb<%d>" % width
+    name = "k_mc<%d, false>" % width if mpr == 1 else "k_mcb<%d>" % width
     return "%s (p=%d, %s, %d trial move%s per traversal)" % (name, p, tune.get("shape", ""), mpr, "" if mpr == 1 else "s")
 
 
@@ -237,8 +237,8 @@ def accuracy(P, x, y, z, q):
 def run_lines(c, moves, M=4, p=6, calls=5):
     """The headline system with M line images per ion besides each Kelvin image, at order p
     (the headline's theta): the chain one move per traversal (kernel time) beside the same
-    chain with the Kelvin image alone, the energy evaluation, and the accuracy of both ends
-    of the chain against the same model summed directly."""
+    chain with the Kelvin image alone, the energy and the energy with its gradient, and the
+    accuracy of both ends of the chain against the same model summed directly."""
     import torch
     from paper_1305_1825_amd import bhmc
     P = dict(c["params"], line_images=M, p=p)
@@ -256,6 +256,14 @@ def run_lines(c, moves, M=4, p=6, calls=5):
     e1.record(s)
     e1.synchronize()
     energy_ms = e0.elapsed_time(e1) / calls
+    t.energy_grad()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(calls):
+        t.energy_grad()
+    e1.record(s)
+    e1.synchronize()
+    grad_ms = e0.elapsed_time(e1) / calls
     t.mc_run(seed=c["seed"], n_moves=moves, step=c["step"])
     fx, fy, fz, fq = (v.cpu().numpy() for v in t.state())
     t.close()
@@ -263,9 +271,11 @@ def run_lines(c, moves, M=4, p=6, calls=5):
     return {"workload": "as the headline at p=%d, plus %d line-image sources per ion "
                         "(sigma = eps_out/(eps_in+eps_out))" % (p, M),
             "sources": (2 + M) * len(x), "chain_moves_per_s": ch["moves_per_s"], "chain_moves": moves,
-            "chain_accepted": ch["accepted"], "kernel": "k_mc<512> (one move per traversal)",
+            "chain_accepted": ch["accepted"],
+            "kernel": "eval_p%d::k_mc<512, true> (the move kernel with the line-image steps, one move per "
+                      "traversal)" % p,
             "kelvin_only_chain_moves_per_s": ck["moves_per_s"],
-            "energy_ms": energy_ms,
+            "energy_ms": energy_ms, "energy_and_gradient_ms": grad_ms,
             "accuracy_start": {k: a0[k] for k in ("E_4_1", "E_rel", "meets_1e-4")},
             "accuracy_end": {k: a1[k] for k in ("E_4_1", "E_rel", "meets_1e-4")}}
 
