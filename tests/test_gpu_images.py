@@ -258,3 +258,46 @@ def test_gradient_after_moves_matches_oracle():
     _, dro, dqo = o.grad()
     assert rel_err(dr.cpu().numpy(), dro) <= 1e-9 and rel_err(dq.cpu().numpy(), dqo) <= 1e-9
     g.close()
+
+
+def test_full_size_bench_configuration():
+    """The bench's multiple-image workload (N = 10^4 colloid ions, M = 4, theta = 0.4,
+    p = 6): energy and a 2000-move chain against the oracle; the gradient by the Euler
+    identity in the charges and by central differences of the GPU energy on sampled
+    components (the oracle's full gradient at this size takes minutes)."""
+    c = W.config_colloid_10k()
+    P = dict(c["params"], theta=0.4, p=6, n0=0, line_images=4)
+    x, y, z, q = (np.array(c[k], dtype=float) for k in "xyzq")
+    say("line images full size: N=%d M=4" % len(x))
+    g, o = bhmc.Tree(P, x, y, z, q), O.Tree(P, x, y, z, q)
+    Eg = g.energy()
+    Eo, phio = o.energy(with_phi=True)
+    mag = P["l_B"] * 0.5 * np.sum(np.abs(q * phio))
+    assert abs(Eg - Eo) <= 1e-13 * mag + 1e-12 * abs(Eo)
+    E2, dr, dq = g.energy_grad()
+    assert abs(E2 - Eg) <= 1e-13 * mag
+    dr, dq = dr.cpu().numpy(), dq.cpu().numpy()
+    Elin = P["l_B"] * P["Q_center"] * np.sum(q / np.sqrt(x * x + y * y + z * z))
+    assert abs(np.dot(q, dq) - (2 * (E2 - Elin) + Elin)) <= 1e-11 * mag
+    rms = np.sqrt(np.mean(dr ** 2))
+    h, bad = 1e-6, 0
+    for i in W.sample_indices(len(x), 6, tag=11):
+        for comp, arr in enumerate((x, y, z)):
+            a1, a2 = arr.copy(), arr.copy()
+            a1[i] += h
+            a2[i] -= h
+            args1 = [a1 if k == comp else (x, y, z)[k] for k in range(3)]
+            args2 = [a2 if k == comp else (x, y, z)[k] for k in range(3)]
+            fd = (bhmc.Tree(P, *args1, q).energy() - bhmc.Tree(P, *args2, q).energy()) / (2 * h)
+            if abs(fd - dr[i, comp]) > 1e-6 * (abs(dr[i, comp]) + rms):
+                bad += 1
+    assert bad <= 1  # a shift across a MAC or cell boundary changes the interaction list
+    rg = g.mc_run(seed=0, n_moves=2000, step=1.0, accept_bits=True)
+    ro = o.mc_run(seed=0, replica=0, move0=0, n_moves=2000, step=1.0)
+    assert np.array_equal(rg["accept"].cpu().numpy(), ro["accept"])
+    xs, ys, zs, _ = (t.cpu().numpy() for t in g.state())
+    xo, yo, zo, _ = o.sources()
+    n = len(x)
+    assert np.array_equal(xs, xo[:n]) and np.array_equal(ys, yo[:n]) and np.array_equal(zs, zo[:n])
+    assert abs(g.energy() - o.energy()) <= 1e-11 * mag
+    g.close()
