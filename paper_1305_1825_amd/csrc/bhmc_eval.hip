@@ -127,6 +127,11 @@ using LRow = const __attribute__((address_space(3))) double*;
 __device__ __forceinline__ GRow grow(const double* p) { return (GRow)p; }
 __device__ __forceinline__ LRow lrow(const double* p) { return (LRow)p; }
 
+// An FP64 add to HBM through a global-qualified pointer: the compiler then knows
+// it cannot write LDS, so LDS loads stay free to move across it.
+using GDbl = __attribute__((address_space(1))) double*;
+__device__ __forceinline__ void gatomic_add(double* p, double v) { __builtin_amdgcn_global_atomic_fadd_f64((GDbl)p, v); }
+
 // The same for single records of the tree in HBM: cell geometry, cell header,
 // a source, a slot's source index, a tracking entry.
 using GInt = const __attribute__((address_space(1))) int*;
@@ -1776,6 +1781,12 @@ struct GradShared {
     static constexpr int FARCAP = 512 + kGradBlock;
     static constexpr int NEARCAP = 256 + kGradBlock;
     static constexpr int NW = kGradBlock / 64;
+    // first in the block, so that every term's LDS address is a row base plus an
+    // immediate offset below 64 KiB (no per-term address registers)
+    union {
+        double mrow[kGradRows][MSTR];        // the moment rows of the far cells of one step, one per row
+        double red[kGradRows][kGT][4];       // the rows' sums of each target at the end
+    };
     uint32_t fc[2][FCAP];          // cell
     uint64_t fm[2][FCAP];          // open | direct << 16 | image inside << 32 | ion inside << 48
     uint32_t farc[FARCAP], farm[FARCAP];
@@ -1786,50 +1797,89 @@ struct GradShared {
     int flag_cell[kGT];
     int nt;
     uint64_t wcnt[2][NW];
-    union {
-        double mrow[kGradRows][MSTR];        // the moment rows of the far cells of one step, one per row
-        double red[kGradRows][kGT][4];       // the rows' sums of each target at the end
-    };
     int err;
 };
 
-// Sum over the 16 lanes of a row, left in every lane of the row: DPP
-// exchanges within the row (lane ^ 1, lane ^ 2, then the mirror images within
-// 8 and within 16 lanes), no memory traffic.
+// A double read from another lane of the same 16-lane row by a DPP control
+// (two 32-bit moves), no memory traffic; every control used here has a source
+// lane inside the row for every lane.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ double row_sum16(double v) {
-    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141>(v);  // row_half_mirror
-    v += dpp_f64<0x140>(v);  // row_mirror
+// Reduce-scatter over the 16 lanes of a row: before, every lane holds x[0..15];
+// after, x[0] of lane l holds the row's sum of x[i(l)], with
+// i(l) = b3 << 3 | (b0 ^ b2) << 2 | (b1 ^ b2) << 1 | b2 for the bits b_j of l in
+// its row.  Four exchange stages with the partners l ^ 8, l ^ 1, l ^ 2 and
+// l ^ 7 (DPP row_ror:8, two quad permutations, row_half_mirror); at each stage
+// a lane keeps the half of its values that its partner does not keep and adds
+// the partner's copy of that half.  15 exchanges instead of the 64 of sixteen
+// row sums, and every lane ends with a distinct index.
+template <int CTRL, int M>
+__device__ __forceinline__ void rs_stage(double (&x)[16], bool up) {
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) {
+        const double lo = x[j], hi = x[j + M / 2];
+        x[j] = (up ? hi : lo) + dpp_f64<CTRL>(up ? lo : hi);
+    }
+}
+__device__ __forceinline__ int rs_index(int l) {
+    return (((l >> 3) & 1) << 3) | (((l ^ (l >> 2)) & 1) << 2) | ((((l >> 1) ^ (l >> 2)) & 1) << 1) | ((l >> 2) & 1);
+}
+__device__ __forceinline__ double row_reduce_scatter16(double (&x)[16], int l) {
+    rs_stage<0x128, 16>(x, (l >> 3) & 1);
+    rs_stage<0xB1, 8>(x, (l ^ (l >> 2)) & 1);
+    rs_stage<0x4E, 4>(x, ((l >> 1) ^ (l >> 2)) & 1);
+    rs_stage<0x141, 2>(x, (l >> 2) & 1);
+    return x[0];
+}
+// Row sums of four values by the first two stages above and two plain sums:
+// every lane gets the sum of value b3 << 1 | (b0 ^ b2), so lanes 0, 1, 8 and 9
+// of the row hold the sums of a, b, c and d.
+__device__ __forceinline__ double row_sum4_scatter(double a, double b, double c, double d, int l) {
+    const bool u1 = (l >> 3) & 1;
+    const double s0 = (u1 ? c : a) + dpp_f64<0x128>(u1 ? a : c);
+    const double s1 = (u1 ? d : b) + dpp_f64<0x128>(u1 ? b : d);
+    const bool u2 = (l ^ (l >> 2)) & 1;
+    double v = (u2 ? s1 : s0) + dpp_f64<0xB1>(u2 ? s0 : s1);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
     return v;
 }
 
 // T up to order p + 1 for one (far cell, target) pair of a row: P and F for
-// the lane's target; the row's sum of w T_n goes to L, term K by lane K mod 16.
+// the lane's target; the row's sums of w T_n go to L sixteen terms at a time,
+// reduce-scattered across the row so that each lane adds one term.
 template <int K, class MP>
-__device__ __forceinline__ void far_rec_row(double (&T)[NTERM1], double Rx, double Ry, double Rz, double ir2,
-                                            MP __restrict__ Mc, double* __restrict__ Lc, double w,
+__device__ __forceinline__ void far_rec_row(double (&T)[NTERM1], double (&C)[16], double Rx, double Ry, double Rz,
+                                            double ir2, MP __restrict__ Mc, double* __restrict__ Lc, double w,
                                             int k, double& phi, double& fx, double& fy, double& fz) {
     if constexpr (K < NTERM1) {
         constexpr TEnt e = TT1.e[K];
         if constexpr (K > 0) t_step<K>(T, Rx, Ry, Rz, ir2);
         if constexpr (K < NTERM) {
             phi = fma(T[K], Mc[K], phi);
-            const double v = row_sum16(w * T[K]);
-            if (k == (K & 15)) unsafeAtomicAdd(Lc + K, v);
+            C[K & 15] = w * T[K];
+            if constexpr ((K & 15) == 15 || K == NTERM - 1) {
+#pragma unroll
+                for (int j = (K & 15) + 1; j < 16; ++j) C[j] = 0.0;
+                const double v = row_reduce_scatter16(C, k);
+                const int idx = (K & ~15) + rs_index(k);
+                if constexpr ((K & ~15) + 16 <= NTERM) gatomic_add(Lc + idx, v);
+                else if (idx < NTERM) gatomic_add(Lc + idx, v);
+            }
         }
         if constexpr (e.x1 >= 0) fx = fma((double)e.n1 * T[K], Mc[e.x1], fx);
         if constexpr (e.y1 >= 0) fy = fma((double)e.n2 * T[K], Mc[e.y1], fy);
         if constexpr (e.z1 >= 0) fz = fma((double)e.n3 * T[K], Mc[e.z1], fz);
-        far_rec_row<K + 1>(T, Rx, Ry, Rz, ir2, Mc, Lc, w, k, phi, fx, fy, fz);
+        // the scheduler may not move work across a boundary every 16 terms: left free it
+        // computes every T_n first and holds them all until the moment rows are read
+        if constexpr ((K & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        far_rec_row<K + 1>(T, C, Rx, Ry, Rz, ir2, Mc, Lc, w, k, phi, fx, fy, fz);
     }
 }
 
@@ -1890,11 +1940,11 @@ __device__ __forceinline__ void grad_rows(const Rep& R, GradShared& S, int far_n
                 const bool act = tk && ((S.farm[j] >> k) & 1u);
                 const double4 g = R.cgeo[c];
                 const double Rx = g.x - xk, Ry = g.y - yk, Rz = g.z - zk;
-                double T[NTERM1];
+                double T[NTERM1], C[16];
                 T[0] = rsqrt_nr(Rx * Rx + Ry * Ry + Rz * Rz);
                 const double ir2 = T[0] * T[0];
                 double phi = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-                far_rec_row<0>(T, Rx, Ry, Rz, ir2, lrow(S.mrow[row]), L + (size_t)c * MSTR, act ? wk : 0.0, k,
+                far_rec_row<0>(T, C, Rx, Ry, Rz, ir2, lrow(S.mrow[row]), L + (size_t)c * MSTR, act ? wk : 0.0, k,
                                phi, fx, fy, fz);
                 if (act) { acc[0] += phi; acc[1] += fx; acc[2] += fy; acc[3] += fz; }
             }
@@ -1923,12 +1973,8 @@ __device__ __forceinline__ void grad_rows(const Rep& R, GradShared& S, int far_n
                 acc[0] += src.w * ir; acc[1] += qi3 * dx; acc[2] += qi3 * dy; acc[3] += qi3 * dz;
                 sx = wk * qi3 * dx; sy = wk * qi3 * dy; sz = wk * qi3 * dz; sq = wk * ir;
             }
-            sx = row_sum16(sx); sy = row_sum16(sy); sz = row_sum16(sz); sq = row_sum16(sq);
-            double4* Gs = G + sid;
-            if (k == 0) unsafeAtomicAdd(&Gs->x, sx);
-            else if (k == 1) unsafeAtomicAdd(&Gs->y, sy);
-            else if (k == 2) unsafeAtomicAdd(&Gs->z, sz);
-            else if (k == 3) unsafeAtomicAdd(&Gs->w, sq);
+            const double sv = row_sum4_scatter(sx, sy, sz, sq, k);
+            if ((k & 6) == 0) gatomic_add(&G[sid].x + (((k >> 3) << 1) | (k & 1)), sv);
         }
     }
 }
