@@ -361,11 +361,19 @@ def run_gradient(theta=0.5, calls=3):
     t.energy()
     e1.record(stream)
     e1.synchronize()
+    # the tree built again from the same positions (what the autograd backward pays first)
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
+    b0.record(stream)
+    t.rebuild()
+    b1.record(stream)
+    b1.synchronize()
     inf = t.info()
     t.close()
     med = float(np.median(ms))
     return dict(workload="N=100000 ions + images, shell 10.5<r<120, theta=%.1f, p=6, leaf 16" % theta,
                 ms_per_gradient=med, ms_energy_only=e0.elapsed_time(e1), ratio_to_energy=med / e0.elapsed_time(e1),
+                ms_build=b0.elapsed_time(b1),
                 ions_per_s=len(c["x"]) / (med / 1000.0), E=E, ncell=inf["ncell"],
                 traffic=traffic("grad", 1))
 

@@ -141,6 +141,7 @@ struct bhmc_tree {
     bhmc::MoveIO* io = nullptr;
     double* eterm = nullptr; int eterm_n = 0;
     char* gwork = nullptr; size_t gwork_bytes = 0;  // gradient workspace
+    int* wide_buf = nullptr;         // grid-wide build of one large replica: sort histograms, level counts
     double* scalar = nullptr;
     double* scratch = nullptr;       // device address of the fixed scratch array on the handle's device
     // HBM frontier regions, allocated the first time a traversal level outgrows its LDS capacity
@@ -478,8 +479,20 @@ static bhmc_status build_list(bhmc_tree* t, const std::vector<int>& list, const 
     st = upload(t);
     if (st) return st;
     bhmc::launch_sources(t->stream, nr, t->reps, dlist, x, y, z, q, x ? doff : nullptr);
-    bhmc::launch_sort(t->stream, nr, t->reps, dlist);
-    bhmc::launch_count(t->stream, nr, t->reps, dlist);
+    const int nsrc0 = t->host[list[0]].nsrc;
+    if (nr == 1 && nsrc0 >= bhmc::kWideBuildMin) {
+        // one large replica: sort and count over a grid of workgroups (same results)
+        if (!t->wide_buf) {
+            const size_t bytes = sizeof(int) * (256 * bhmc::kSortGridMax + bhmc::kCountLevels);
+            HIP_TRY(hipMalloc(&t->wide_buf, bytes));
+            HIP_TRY(hipMemsetAsync(t->wide_buf, 0, bytes, t->stream));
+        }
+        bhmc::launch_sort_wide(t->stream, t->reps, list[0], nsrc0, t->wide_buf);
+        bhmc::launch_count_wide(t->stream, t->reps, list[0], nsrc0, t->wide_buf + 256 * bhmc::kSortGridMax);
+    } else {
+        bhmc::launch_sort(t->stream, nr, t->reps, dlist);
+        bhmc::launch_count(t->stream, nr, t->reps, dlist);
+    }
     HIP_TRY(hipGetLastError());
     if ((st = download(t))) return st;
     for (int r : list) {
@@ -515,7 +528,7 @@ static void destroy(bhmc_tree* t) {
     for (void* p : t->arena2) if (p) hipFree(p);
     hipFree(t->reps); hipFree(t->queue); hipFree(t->list_all); hipFree(t->list_one); hipFree(t->list_rest);
     hipFree(t->sweep_add); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar); hipFree(t->gwork);
-    hipFree(t->spill);
+    hipFree(t->spill); hipFree(t->wide_buf);
     if (t->host) hipHostFree(t->host);
     if (t->pin) hipHostFree(t->pin);
     delete t;

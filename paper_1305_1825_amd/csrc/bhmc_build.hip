@@ -61,13 +61,57 @@ k_sources(Rep* reps, const int* rep_list, const double* x, const double* y, cons
     if (threadIdx.x == 0) R.status = (bad & 1) ? -1 : ((bad & 2) ? -2 : 0);
 }
 
-// Stable LSD radix sort, 8 passes of 8 bits.  Each pass: LDS histogram,
-// exclusive scan, then tiles of BLOCK items scattered in order; inside a tile
-// an item's rank among equal digits comes from a wave-wide match (8 ballots)
-// plus the counts of the waves before it.
+constexpr int kSortNW = kBuildBlock / 64;
+
+// One tile of a stable LSD pass: the items [base, base + kBuildBlock) of (ka, va)
+// below n go to (kb, vb) at off[d] plus their rank among the tile's items of
+// digit d, and off[] advances by the tile's counts.  An item's rank comes from a
+// wave-wide match of its digit (8 ballots) plus the counts of the waves before
+// it (wcnt, zero on entry and on return).
+__device__ __forceinline__ void sort_tile(const uint64_t* ka, const int* va, uint64_t* kb, int* vb, int base, int n,
+                                          int shift, int* off, int (*wcnt)[256], int* tile_tot) {
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    const int k = base + tid;
+    const bool valid = k < n;
+    const uint64_t key = valid ? ka[k] : 0;
+    const int val = valid ? va[k] : 0;
+    const int dig = (int)((key >> shift) & 255);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (dig >> b) & 1;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int rank = __popcll(peers & below);
+    const bool leader = valid && rank == 0;
+    if (leader) wcnt[w][dig] = __popcll(peers);
+    __syncthreads();
+    if (tid < 256) {
+        int s = 0;
+        for (int ww = 0; ww < kSortNW; ++ww) { int c = wcnt[ww][tid]; wcnt[ww][tid] = s; s += c; }
+        tile_tot[tid] = s;
+    }
+    __syncthreads();
+    if (valid) {
+        const int pos = off[dig] + wcnt[w][dig] + rank;
+        kb[pos] = key;
+        vb[pos] = val;
+    }
+    __syncthreads();
+    if (tid < 256) {
+        off[tid] += tile_tot[tid];
+        for (int ww = 0; ww < kSortNW; ++ww) wcnt[ww][tid] = 0;
+    }
+    __syncthreads();
+}
+
+// Stable LSD radix sort, 8 passes of 8 bits, one workgroup per replica.  Each
+// pass: LDS histogram, exclusive scan, then the tiles scattered in order.
 __global__ void __launch_bounds__(kBuildBlock)
 k_sort(Rep* reps, const int* rep_list) {
-    constexpr int NW = kBuildBlock / 64;
+    constexpr int NW = kSortNW;
     Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
     const int n = R.nsrc;
     __shared__ int hist[256];
@@ -76,7 +120,7 @@ k_sort(Rep* reps, const int* rep_list) {
     __shared__ int skip;
     uint64_t* ka = R.keys; int* va = R.perm;
     uint64_t* kb = R.ktmp; int* vb = R.ptmp;
-    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    const int tid = threadIdx.x;
     for (int k = tid; k < NW * 256; k += kBuildBlock) (&wcnt[0][0])[k] = 0;
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
@@ -95,42 +139,8 @@ k_sort(Rep* reps, const int* rep_list) {
             for (int d = 0; d < 256; ++d) { int c = hist[d]; hist[d] = s; s += c; }
         }
         __syncthreads();
-        for (int base = 0; base < n; base += kBuildBlock) {
-            const int k = base + tid;
-            const bool valid = k < n;
-            uint64_t key = valid ? ka[k] : 0;
-            int val = valid ? va[k] : 0;
-            const int dig = (int)((key >> shift) & 255);
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool bit = (dig >> b) & 1;
-                uint64_t m = __ballot(bit);
-                peers &= bit ? m : ~m;
-            }
-            const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-            const int rank = __popcll(peers & below);
-            const bool leader = valid && rank == 0;
-            if (leader) wcnt[w][dig] = __popcll(peers);
-            __syncthreads();
-            if (tid < 256) {
-                int s = 0;
-                for (int ww = 0; ww < NW; ++ww) { int c = wcnt[ww][tid]; wcnt[ww][tid] = s; s += c; }
-                tile_tot[tid] = s;
-            }
-            __syncthreads();
-            if (valid) {
-                const int pos = hist[dig] + wcnt[w][dig] + rank;
-                kb[pos] = key;
-                vb[pos] = val;
-            }
-            __syncthreads();
-            if (tid < 256) {
-                hist[tid] += tile_tot[tid];
-                for (int ww = 0; ww < NW; ++ww) wcnt[ww][tid] = 0;
-            }
-            __syncthreads();
-        }
+        for (int base = 0; base < n; base += kBuildBlock)
+            sort_tile(ka, va, kb, vb, base, n, shift, hist, wcnt, tile_tot);
         uint64_t* tk = ka; ka = kb; kb = tk;
         int* tv = va; va = vb; vb = tv;
     }
@@ -140,6 +150,69 @@ k_sort(Rep* reps, const int* rep_list) {
     }
 }
 
+// The same sort for one large replica over a grid of workgroups, three launches
+// per pass: block histograms, one scan, block scatters.  Block b takes the tiles
+// [b T, (b + 1) T) (T tiles per block); the (digit, block) counts are scanned in
+// digit-major order, so each block's items of digit d land after every item of a
+// smaller digit and after those of digit d in earlier blocks: the order is the
+// one of the sort above.  Every pass runs (a constant digit moves nothing), so
+// the result ends in keys / perm after the eighth.
+__global__ void __launch_bounds__(kBuildBlock)
+k_sort_hist(const Rep* reps, int r, int pass, int tiles_per_block, int* hist) {
+    const Rep& R = reps[r];
+    const int n = R.nsrc, shift = 8 * pass;
+    const uint64_t* ka = (pass & 1) ? R.ktmp : R.keys;
+    __shared__ int h[256];
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
+    __syncthreads();
+    const long long lo = (long long)blockIdx.x * tiles_per_block * kBuildBlock;
+    const int hi = (int)std::min<long long>(n, lo + (long long)tiles_per_block * kBuildBlock);
+    for (int k = (int)lo + threadIdx.x; k < hi; k += kBuildBlock) atomicAdd(&h[(ka[k] >> shift) & 255], 1);
+    __syncthreads();
+    if (threadIdx.x < 256) hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of m counts in place, one workgroup: each thread sums a
+// contiguous run, the run sums are scanned in LDS (Hillis-Steele), and each
+// thread writes its run's prefixes.
+__global__ void __launch_bounds__(kBuildBlock) k_sort_scan(int* v, int m) {
+    __shared__ int part[2][kBuildBlock];
+    const int tid = threadIdx.x;
+    const int per = (m + kBuildBlock - 1) / kBuildBlock;
+    const int lo = std::min(m, tid * per), hi = std::min(m, lo + per);
+    int s = 0;
+    for (int k = lo; k < hi; ++k) s += v[k];
+    int cur = 0;
+    part[0][tid] = s;
+    __syncthreads();
+    for (int d = 1; d < kBuildBlock; d <<= 1) {
+        part[cur ^ 1][tid] = part[cur][tid] + (tid >= d ? part[cur][tid - d] : 0);
+        cur ^= 1;
+        __syncthreads();
+    }
+    int run = part[cur][tid] - s;  // exclusive prefix of this run
+    for (int k = lo; k < hi; ++k) { const int c = v[k]; v[k] = run; run += c; }
+}
+
+__global__ void __launch_bounds__(kBuildBlock)
+k_sort_scatter(Rep* reps, int r, int pass, int tiles_per_block, const int* hist) {
+    Rep& R = reps[r];
+    const int n = R.nsrc, shift = 8 * pass;
+    const uint64_t* ka = (pass & 1) ? R.ktmp : R.keys;
+    const int* va = (pass & 1) ? R.ptmp : R.perm;
+    uint64_t* kb = (pass & 1) ? R.keys : R.ktmp;
+    int* vb = (pass & 1) ? R.perm : R.ptmp;
+    __shared__ int off[256];
+    __shared__ int wcnt[kSortNW][256];
+    __shared__ int tile_tot[256];
+    for (int k = threadIdx.x; k < kSortNW * 256; k += kBuildBlock) (&wcnt[0][0])[k] = 0;
+    if (threadIdx.x < 256) off[threadIdx.x] = hist[threadIdx.x * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const long long lo = (long long)blockIdx.x * tiles_per_block * kBuildBlock;
+    const int hi = (int)std::min<long long>(n, lo + (long long)tiles_per_block * kBuildBlock);
+    for (int base = (int)lo; base < hi; base += kBuildBlock) sort_tile(ka, va, kb, vb, base, hi, shift, off, wcnt, tile_tot);
+}
+
 // first index in [lo, hi) whose key is >= v
 __device__ __forceinline__ int lower_bound_key(const uint64_t* keys, int lo, int hi, uint64_t v) {
     while (lo < hi) {
@@ -147,6 +220,24 @@ __device__ __forceinline__ int lower_bound_key(const uint64_t* keys, int lo, int
         if (keys[mid] < v) lo = mid + 1; else hi = mid;
     }
     return lo;
+}
+
+// Cell, leaf and slot counts of a replica with `total` split cells, the deepest
+// at level depth - 1.
+__device__ __forceinline__ void set_cell_counts(Rep& R, int total, int depth) {
+    R.nsplit = total;
+    R.ncell = 1 + 8 * total;
+    R.nleaf = R.ncell - total;
+    R.depth = depth;
+    // sum_leaves max(count, cap) <= nsrc + nleaf * leaf_cap; every slot index must fit an int
+    const long long pool = (long long)R.slack * ((long long)R.nsrc + (long long)R.nleaf * R.leaf_cap) +
+                           (2ll + R.nline) * R.nleaf;
+    if (pool > 0x7FFFFFFFll - 64) {
+        R.pool = 0;
+        R.status = -4;
+    } else {
+        R.pool = (int)pool;
+    }
 }
 
 // A cell (level l, prefix P) is split iff it holds more than leaf_cap sources
@@ -181,21 +272,40 @@ k_count(Rep* reps, const int* rep_list) {
         __syncthreads();
         if (c == 0) break;
     }
-    if (threadIdx.x == 0) {
-        R.nsplit = total;
-        R.ncell = 1 + 8 * total;
-        R.nleaf = R.ncell - total;
-        R.depth = depth;
-        // sum_leaves max(count, cap) <= nsrc + nleaf * leaf_cap; every slot index must fit an int
-        const long long pool = (long long)R.slack * ((long long)R.nsrc + (long long)R.nleaf * R.leaf_cap) +
-                               (2ll + R.nline) * R.nleaf;
-        if (pool > 0x7FFFFFFFll - 64) {
-            R.pool = 0;
-            R.status = -4;
-        } else {
-            R.pool = (int)pool;
-        }
+    if (threadIdx.x == 0) set_cell_counts(R, total, depth);
+}
+
+// The same count for one large replica over a grid: thread k takes key k at
+// every level where it starts a run of equal prefix, and stops at the first
+// such run that is not split (its runs below are parts of it).  Per-level
+// counts go to cnt[] (zero on entry); k_count_finish sums them and zeroes cnt.
+__global__ void __launch_bounds__(kBuildBlock) k_count_wide(const Rep* reps, int r, int* cnt) {
+    const Rep& R = reps[r];
+    const int n = R.nsrc;
+    const int k = blockIdx.x * kBuildBlock + threadIdx.x;
+    if (k >= n) return;
+    const uint64_t* keys = R.keys;
+    const uint64_t key = keys[k], prev = k > 0 ? keys[k - 1] : 0;
+    for (int l = 0; l < R.max_depth; ++l) {
+        const int shift = 63 - 3 * l;
+        const uint64_t P = key >> shift;
+        if (k > 0 && (prev >> shift) == P) continue;
+        const uint64_t next = (P + 1) << shift;
+        const int e = (l == 0) ? n : lower_bound_key(keys, k, n, next);
+        if (e - k <= R.leaf_cap) break;
+        atomicAdd(&cnt[l], 1);
     }
+}
+
+__global__ void k_count_finish(Rep* reps, int r, int* cnt) {
+    Rep& R = reps[r];
+    int total = 0, depth = 0;
+    for (int l = 0; l < kCountLevels; ++l) {
+        total += cnt[l];
+        if (cnt[l]) depth = l + 1;
+        cnt[l] = 0;
+    }
+    set_cell_counts(R, total, depth);
 }
 
 __device__ __forceinline__ void cell_geometry(const Rep& R, int level, uint64_t kmin, double4& g) {
@@ -450,6 +560,21 @@ void launch_sort(hipStream_t s, int nrep, Rep* reps, const int* list) {
 }
 void launch_count(hipStream_t s, int nrep, Rep* reps, const int* list) {
     hipLaunchKernelGGL(k_count, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
+}
+void launch_sort_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* hist) {
+    const int tiles = (nsrc + kBuildBlock - 1) / kBuildBlock;
+    const int tpb = (tiles + kSortGridMax - 1) / kSortGridMax;
+    const int grid = std::max(1, (tiles + tpb - 1) / tpb);
+    for (int pass = 0; pass < 8; ++pass) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kBuildBlock), 0, s, reps, r, pass, tpb, hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kBuildBlock), 0, s, hist, 256 * grid);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kBuildBlock), 0, s, reps, r, pass, tpb, hist);
+    }
+}
+void launch_count_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* cnt) {
+    hipLaunchKernelGGL(k_count_wide, dim3(std::max(1, (nsrc + kBuildBlock - 1) / kBuildBlock)), dim3(kBuildBlock), 0, s,
+                       reps, r, cnt);
+    hipLaunchKernelGGL(k_count_finish, dim3(1), dim3(1), 0, s, reps, r, cnt);
 }
 void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list) {
     hipLaunchKernelGGL(k_topology, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);

@@ -1876,9 +1876,6 @@ __device__ __forceinline__ void far_rec_row(double (&T)[NTERM1], double (&C)[16]
         if constexpr (e.x1 >= 0) fx = fma((double)e.n1 * T[K], Mc[e.x1], fx);
         if constexpr (e.y1 >= 0) fy = fma((double)e.n2 * T[K], Mc[e.y1], fy);
         if constexpr (e.z1 >= 0) fz = fma((double)e.n3 * T[K], Mc[e.z1], fz);
-        // the scheduler may not move work across a boundary every 16 terms: left free it
-        // computes every T_n first and holds them all until the moment rows are read
-        if constexpr ((K & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         far_rec_row<K + 1>(T, C, Rx, Ry, Rz, ir2, Mc, Lc, w, k, phi, fx, fy, fz);
     }
 }

@@ -42,6 +42,14 @@ void launch_sources(hipStream_t s, int nrep, Rep* reps, const int* list, const d
                     const double* y, const double* z, const double* q, const long long* ion_off);
 void launch_sort(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_count(hipStream_t s, int nrep, Rep* reps, const int* list);
+// One large replica over a grid of workgroups, with the same results: the sort
+// uses hist (256 * kSortGridMax ints), the count cnt (kCountLevels ints, zero
+// before the call and zero again after it).
+constexpr int kSortGridMax = 256;
+constexpr int kCountLevels = 64;
+constexpr int kWideBuildMin = 32768;  // sources from which a single-replica build goes wide
+void launch_sort_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* hist);
+void launch_count_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* cnt);
 void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_leaves(hipStream_t s, int nrep, Rep* reps, const int* list);
 // host / host_list: the host mirror of the descriptors (sizes and levels as counted) and the replicas

@@ -90,8 +90,15 @@ def test_maximum_ion_count_with_images():
     P = W.shell_params(20.0, -1000.0, 20.5, 400.0, theta=0.5, p=2, leaf_cap=16, l_B=1.0)
     say("2^22 ions + images, p=2, 300 moves")
     g = bhmc.Tree(P, x, y, z, q)
-    rg = g.mc_run(seed=0, n_moves=300, step=1.0, accept_bits=True)
     o = O.Tree(P, x, y, z, q)
+    # the GPU sorts and counts this tree over a grid of workgroups
+    kg, pg = g.sorted()
+    ko, po = o.sorted()
+    assert np.array_equal(kg, ko) and np.array_equal(pg, po)
+    for key in ("ncell", "nleaf", "depth"):
+        assert g.info()[key] == o.info()[key], key
+    del kg, pg, ko, po
+    rg = g.mc_run(seed=0, n_moves=300, step=1.0, accept_bits=True)
     ro = o.mc_run(seed=0, replica=0, move0=0, n_moves=300, step=1.0)
     bits = rg["accept"].cpu().numpy()
     first = np.nonzero(bits != ro["accept"])[0]

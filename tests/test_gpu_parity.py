@@ -92,10 +92,17 @@ def phi_scale(o, P, i, r):
 
 
 # ---------------------------------------------------------------- tree build
-@pytest.mark.parametrize("case", ["cube1k", "colloid2k", "colloid10k", "uniform_paper", "tiny"])
+@pytest.mark.parametrize("case", ["cube1k", "colloid2k", "colloid10k", "uniform_paper", "tiny", "colloid20k",
+                                  "cube40k"])
 def test_build_matches_oracle(case):
+    # colloid20k (40,000 sources) and cube40k (40,000 sources, no images) are built over a
+    # grid of workgroups (one replica of at least 32,768 sources), the others by one workgroup
     if case == "cube1k":
         c = W.config_cube_1k()
+    elif case == "colloid20k":
+        c = W.config_colloid_10k(n=20000)
+    elif case == "cube40k":
+        c = W.config_cube_1k(n=40000)
     elif case == "colloid2k":
         c = W.config_colloid_10k(n=2000)
     elif case == "colloid10k":
@@ -110,6 +117,45 @@ def test_build_matches_oracle(case):
     cg, co, mg, mo = assert_same_tree(g, o)
     assert_moments(cg, co, mg, mo, o, P["p"])
     assert_same_slots(g, o)
+
+
+@pytest.mark.parametrize("n", [16384, 16385, 50001])
+def test_grid_build_equals_workgroup_build(n):
+    """A single large replica is sorted and counted over a grid of workgroups; a handle of
+    two replicas builds both by one workgroup each.  Same keys, order, cells, leaves and slots;
+    rebuilding one replica of the pair (a list of one) takes the grid path again."""
+    c = W.config_colloid_10k(n=n)
+    say("grid build", n)
+    P = c["params"]
+    g1 = bhmc.Tree(P, c["x"], c["y"], c["z"], c["q"])
+    cat = [np.concatenate([c[k], c[k]]) for k in ("x", "y", "z", "q")]
+    g2 = bhmc.Tree([P, P], *cat, n_per_replica=[n, n])
+
+    def same(a, ra, b, rb):
+        ka, pa = a.sorted(ra)
+        kb, pb = b.sorted(rb)
+        assert np.array_equal(ka, kb) and np.array_equal(pa, pb)
+        ca, cb = a.cells(ra, moments=True), b.cells(rb, moments=True)
+        for k in ca:
+            if k == "M":
+                assert np.allclose(ca[k], cb[k], rtol=1e-13, atol=1e-13 * np.max(np.abs(ca[k])))
+            else:
+                assert np.array_equal(ca[k], cb[k]), k
+        la, lb = a.leaves(ra), b.leaves(rb)
+        for k in la:
+            assert np.array_equal(la[k], lb[k]), k
+        # occupied slots only: a leaf's spare slots hold nothing defined
+        for ma, mb in zip(a.leaf_members(ra), b.leaf_members(rb)):
+            assert np.array_equal(ma, mb)
+
+    same(g1, 0, g2, 0)
+    same(g1, 0, g2, 1)
+    g2.rebuild(1)
+    same(g1, 0, g2, 1)
+    g1.rebuild(0)
+    same(g1, 0, g2, 0)
+    g1.close()
+    g2.close()
 
 
 # ---------------------------------------------------------------- energy change and energy
