@@ -506,7 +506,10 @@ static bhmc_status build_list(bhmc_tree* t, const std::vector<int>& list, const 
     for (int r : list) if ((st = alloc_phase2(t, r))) return st;
     if ((st = upload(t))) return st;
     bhmc::launch_topology(t->stream, nr, t->reps, dlist);
-    bhmc::launch_leaves(t->stream, nr, t->reps, dlist);
+    if (nr == 1 && nsrc0 >= bhmc::kWideBuildMin)
+        bhmc::launch_leaves_wide(t->stream, t->reps, dlist, list[0], t->host[list[0]].nleaf);
+    else
+        bhmc::launch_leaves(t->stream, nr, t->reps, dlist);
     HIP_TRY(hipGetLastError());
     if ((st = download(t))) return st;  // cells per level size the moment launches
     for (int r : list)

@@ -401,10 +401,27 @@ k_topology(Rep* reps, const int* rep_list) {
     }
 }
 
+// Members of leaf l in sorted order, with their tracking entries.
+__device__ __forceinline__ void fill_leaf(Rep& R, int l) {
+    const int c = R.lcell[l];
+    if (c < 0 || c >= R.ncell) { R.status = -8; return; }
+    const int b = R.cbegin[c], e = R.cend[c], base = R.lbase[l];
+    if (b < 0 || e > R.nsrc || b > e || base + (e - b) > R.pool) { R.status = -8; return; }
+    R.cm[c].z = base;
+    for (int k = b; k < e; ++k) {
+        const int s = R.perm[k];
+        if (s < 0 || s >= R.nsrc) { R.status = -8; continue; }
+        R.pool4[base + k - b] = R.src[s];
+        R.pidx[base + k - b] = s;
+        R.track[s] = make_int2(c, k - b);
+    }
+}
+
 // Leaf index arrays: bases by an exclusive scan of the capacities; members
-// in sorted order; tracking = (leaf, slot) of every source.
+// in sorted order; tracking = (leaf, slot) of every source.  With fill = 0
+// only the bases (k_leaves_fill then fills the leaves over a grid).
 __global__ void __launch_bounds__(kBuildBlock)
-k_leaves(Rep* reps, const int* rep_list) {
+k_leaves(Rep* reps, const int* rep_list, int fill) {
     Rep& R = reps[rep_list ? rep_list[blockIdx.x] : blockIdx.x];
     __shared__ uint64_t wsum[kBuildBlock / 64 + 1];
     __shared__ int carry;
@@ -424,21 +441,17 @@ k_leaves(Rep* reps, const int* rep_list) {
     }
     if (threadIdx.x == 0 && carry > R.pool) R.status = -5;
     __syncthreads();
-    if (carry > R.pool || R.status) return;  // uniform: nothing is written past the pool
-    for (int l = threadIdx.x; l < nl; l += blockDim.x) {
-        const int c = R.lcell[l];
-        if (c < 0 || c >= R.ncell) { R.status = -8; continue; }
-        const int b = R.cbegin[c], e = R.cend[c], base = R.lbase[l];
-        if (b < 0 || e > R.nsrc || b > e || base + (e - b) > R.pool) { R.status = -8; continue; }
-        R.cm[c].z = base;
-        for (int k = b; k < e; ++k) {
-            const int s = R.perm[k];
-            if (s < 0 || s >= R.nsrc) { R.status = -8; continue; }
-            R.pool4[base + k - b] = R.src[s];
-            R.pidx[base + k - b] = s;
-            R.track[s] = make_int2(c, k - b);
-        }
-    }
+    if (carry > R.pool || R.status || !fill) return;  // uniform: nothing is written past the pool
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) fill_leaf(R, l);
+}
+
+// The leaves of one replica, one thread per leaf over a grid (after k_leaves with fill = 0;
+// a status set by the scan leaves every leaf unwritten).
+__global__ void __launch_bounds__(256) k_leaves_fill(Rep* reps, int r) {
+    Rep& R = reps[r];
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= R.nleaf || R.status) return;
+    fill_leaf(R, l);
 }
 
 // multi-index table in graded order, shared by the build kernels
@@ -580,7 +593,11 @@ void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list) {
     hipLaunchKernelGGL(k_topology, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
 }
 void launch_leaves(hipStream_t s, int nrep, Rep* reps, const int* list) {
-    hipLaunchKernelGGL(k_leaves, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
+    hipLaunchKernelGGL(k_leaves, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list, 1);
+}
+void launch_leaves_wide(hipStream_t s, Rep* reps, const int* list, int r, int nleaf) {
+    hipLaunchKernelGGL(k_leaves, dim3(1), dim3(kBuildBlock), 0, s, reps, list, 0);
+    hipLaunchKernelGGL(k_leaves_fill, dim3(std::max(1, (nleaf + 255) / 256)), dim3(256), 0, s, reps, r);
 }
 static unsigned chunks(long long items) {
     long long b = (items + kMomBlock - 1) / kMomBlock;

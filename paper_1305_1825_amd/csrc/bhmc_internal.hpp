@@ -50,6 +50,7 @@ constexpr int kCountLevels = 64;
 constexpr int kWideBuildMin = 32768;  // sources from which a single-replica build goes wide
 void launch_sort_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* hist);
 void launch_count_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* cnt);
+void launch_leaves_wide(hipStream_t s, Rep* reps, const int* list, int r, int nleaf);
 void launch_topology(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_leaves(hipStream_t s, int nrep, Rep* reps, const int* list);
 // host / host_list: the host mirror of the descriptors (sizes and levels as counted) and the replicas
