@@ -1876,6 +1876,9 @@ __device__ __forceinline__ void far_rec_row(double (&T)[NTERM1], double (&C)[16]
         if constexpr (e.x1 >= 0) fx = fma((double)e.n1 * T[K], Mc[e.x1], fx);
         if constexpr (e.y1 >= 0) fy = fma((double)e.n2 * T[K], Mc[e.y1], fy);
         if constexpr (e.z1 >= 0) fz = fma((double)e.n3 * T[K], Mc[e.z1], fz);
+        // a scheduling boundary every 16 terms keeps the T_n of one stretch from being
+        // computed far ahead of their use (measured 3 % faster at p = 6)
+        if constexpr ((K & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         far_rec_row<K + 1>(T, C, Rx, Ry, Rz, ir2, Mc, Lc, w, k, phi, fx, fy, fz);
     }
 }
