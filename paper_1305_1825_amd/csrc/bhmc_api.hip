@@ -478,18 +478,20 @@ static bhmc_status build_list(bhmc_tree* t, const std::vector<int>& list, const 
         if (!t->host[r].src && (st = alloc_phase1(t, r))) return st;
     st = upload(t);
     if (st) return st;
-    bhmc::launch_sources(t->stream, nr, t->reps, dlist, x, y, z, q, x ? doff : nullptr);
     const int nsrc0 = t->host[list[0]].nsrc;
     if (nr == 1 && nsrc0 >= bhmc::kWideBuildMin) {
-        // one large replica: sort and count over a grid of workgroups (same results)
+        // one large replica: sources, sort and count over a grid of workgroups (same results)
         if (!t->wide_buf) {
-            const size_t bytes = sizeof(int) * (256 * bhmc::kSortGridMax + bhmc::kCountLevels);
+            const size_t bytes = sizeof(int) * (256 * bhmc::kSortGridMax + bhmc::kCountLevels + 64);
             HIP_TRY(hipMalloc(&t->wide_buf, bytes));
             HIP_TRY(hipMemsetAsync(t->wide_buf, 0, bytes, t->stream));
         }
+        bhmc::launch_sources_wide(t->stream, t->reps, list[0], t->host[list[0]].n, x, y, z, q, x ? doff : nullptr,
+                                  t->wide_buf + 256 * bhmc::kSortGridMax + bhmc::kCountLevels);
         bhmc::launch_sort_wide(t->stream, t->reps, list[0], nsrc0, t->wide_buf);
         bhmc::launch_count_wide(t->stream, t->reps, list[0], nsrc0, t->wide_buf + 256 * bhmc::kSortGridMax);
     } else {
+        bhmc::launch_sources(t->stream, nr, t->reps, dlist, x, y, z, q, x ? doff : nullptr);
         bhmc::launch_sort(t->stream, nr, t->reps, dlist);
         bhmc::launch_count(t->stream, nr, t->reps, dlist);
     }

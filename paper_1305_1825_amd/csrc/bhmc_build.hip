@@ -16,6 +16,46 @@ namespace bhmc {
 
 constexpr int kBuildBlock = 1024;
 
+// Ion i of replica R (from the inputs, or from the replica's own ions when x is
+// null) with its Kelvin image and line images, keys and identity permutation;
+// returns 1 for a non-finite input, 2 for a source outside the shell or root.
+__device__ __forceinline__ int make_sources(Rep& R, int i, const double* x, const double* y, const double* z,
+                                            const double* q, long long off) {
+    const int n = R.n;
+    int bad = 0;
+    double xi, yi, zi, qi;
+    if (x) {
+        xi = x[off + i]; yi = y[off + i]; zi = z[off + i]; qi = q[off + i];
+    } else {  // rebuild from the replica's own current ions
+        double4 s = R.src[i];
+        xi = s.x; yi = s.y; zi = s.z; qi = s.w;
+    }
+    if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(qi))) bad |= 1;
+    else if (outside(R, xi, yi, zi) || !in_root(R, xi, yi, zi)) bad |= 2;
+    R.src[i] = make_double4(xi, yi, zi, qi);
+    R.keys[i] = morton_key(R, xi, yi, zi);
+    R.perm[i] = i;
+    if (R.images) {
+        double4 im = kelvin(R, xi, yi, zi, qi);
+        if (!in_root(R, im.x, im.y, im.z)) bad |= 2;
+        R.src[n + i] = im;
+        R.keys[n + i] = morton_key(R, im.x, im.y, im.z);
+        R.perm[n + i] = n + i;
+        // line images (multiple-image model): source 2n + m n + i at t_m r_K, charge c_m q_K
+        for (int m = 0; m < R.nline; ++m) {
+            const int s = 2 * n + m * n + i;
+            const double4 li = make_double4(R.line_t[m] * im.x, R.line_t[m] * im.y, R.line_t[m] * im.z,
+                                            R.line_c[m] * im.w);
+            R.src[s] = li;
+            R.keys[s] = morton_key(R, li.x, li.y, li.z);
+            R.perm[s] = s;
+        }
+    }
+    return bad;
+}
+
+__device__ __forceinline__ int status_of(int bad) { return (bad & 1) ? -1 : ((bad & 2) ? -2 : 0); }
+
 __global__ void __launch_bounds__(kBuildBlock)
 k_sources(Rep* reps, const int* rep_list, const double* x, const double* y, const double* z,
           const double* q, const long long* ion_off) {
@@ -26,39 +66,28 @@ k_sources(Rep* reps, const int* rep_list, const double* x, const double* y, cons
     __syncthreads();
     int my_bad = 0;
     const long long off = ion_off ? ion_off[blockIdx.x] : 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double xi, yi, zi, qi;
-        if (x) {
-            xi = x[off + i]; yi = y[off + i]; zi = z[off + i]; qi = q[off + i];
-        } else {  // rebuild from the replica's own current ions
-            double4 s = R.src[i];
-            xi = s.x; yi = s.y; zi = s.z; qi = s.w;
-        }
-        if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(qi))) my_bad |= 1;
-        else if (outside(R, xi, yi, zi) || !in_root(R, xi, yi, zi)) my_bad |= 2;
-        R.src[i] = make_double4(xi, yi, zi, qi);
-        R.keys[i] = morton_key(R, xi, yi, zi);
-        R.perm[i] = i;
-        if (R.images) {
-            double4 im = kelvin(R, xi, yi, zi, qi);
-            if (!in_root(R, im.x, im.y, im.z)) my_bad |= 2;
-            R.src[n + i] = im;
-            R.keys[n + i] = morton_key(R, im.x, im.y, im.z);
-            R.perm[n + i] = n + i;
-            // line images (multiple-image model): source 2n + m n + i at t_m r_K, charge c_m q_K
-            for (int m = 0; m < R.nline; ++m) {
-                const int s = 2 * n + m * n + i;
-                const double4 li = make_double4(R.line_t[m] * im.x, R.line_t[m] * im.y, R.line_t[m] * im.z,
-                                                R.line_c[m] * im.w);
-                R.src[s] = li;
-                R.keys[s] = morton_key(R, li.x, li.y, li.z);
-                R.perm[s] = s;
-            }
-        }
-    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) my_bad |= make_sources(R, i, x, y, z, q, off);
     if (my_bad) atomicOr(&bad, my_bad);
     __syncthreads();
-    if (threadIdx.x == 0) R.status = (bad & 1) ? -1 : ((bad & 2) ? -2 : 0);
+    if (threadIdx.x == 0) R.status = status_of(bad);
+}
+
+// The same for one large replica, one thread per ion over a grid; the checks
+// gather in *flag (zero on entry) and k_sources_finish turns them into the
+// replica's status and zeroes *flag.
+__global__ void __launch_bounds__(256) k_sources_wide(Rep* reps, int r, const double* x, const double* y,
+                                                      const double* z, const double* q, const long long* ion_off,
+                                                      int* flag) {
+    Rep& R = reps[r];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R.n) return;
+    const int b = make_sources(R, i, x, y, z, q, ion_off ? ion_off[0] : 0);
+    if (b) atomicOr(flag, b);
+}
+
+__global__ void k_sources_finish(Rep* reps, int r, int* flag) {
+    reps[r].status = status_of(*flag);
+    *flag = 0;
 }
 
 constexpr int kSortNW = kBuildBlock / 64;
@@ -172,16 +201,22 @@ k_sort_hist(const Rep* reps, int r, int pass, int tiles_per_block, int* hist) {
     if (threadIdx.x < 256) hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of m counts in place, one workgroup: each thread sums a
-// contiguous run, the run sums are scanned in LDS (Hillis-Steele), and each
+// Exclusive scan of m <= 64 * kBuildBlock counts in place, one workgroup: each
+// thread loads its contiguous run of at most 64 counts at once (all loads in
+// flight together), the run sums are scanned in LDS (Hillis-Steele), and each
 // thread writes its run's prefixes.
+constexpr int kScanRun = 64;
 __global__ void __launch_bounds__(kBuildBlock) k_sort_scan(int* v, int m) {
     __shared__ int part[2][kBuildBlock];
     const int tid = threadIdx.x;
     const int per = (m + kBuildBlock - 1) / kBuildBlock;
     const int lo = std::min(m, tid * per), hi = std::min(m, lo + per);
+    int c[kScanRun];
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) c[j] = lo + j < hi ? v[lo + j] : 0;
     int s = 0;
-    for (int k = lo; k < hi; ++k) s += v[k];
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) s += c[j];
     int cur = 0;
     part[0][tid] = s;
     __syncthreads();
@@ -191,7 +226,11 @@ __global__ void __launch_bounds__(kBuildBlock) k_sort_scan(int* v, int m) {
         __syncthreads();
     }
     int run = part[cur][tid] - s;  // exclusive prefix of this run
-    for (int k = lo; k < hi; ++k) { const int c = v[k]; v[k] = run; run += c; }
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+        if (lo + j < hi) v[lo + j] = run;
+        run += c[j];
+    }
 }
 
 __global__ void __launch_bounds__(kBuildBlock)
@@ -573,6 +612,12 @@ void launch_sort(hipStream_t s, int nrep, Rep* reps, const int* list) {
 }
 void launch_count(hipStream_t s, int nrep, Rep* reps, const int* list) {
     hipLaunchKernelGGL(k_count, dim3(nrep), dim3(kBuildBlock), 0, s, reps, list);
+}
+void launch_sources_wide(hipStream_t s, Rep* reps, int r, int n, const double* x, const double* y,
+                         const double* z, const double* q, const long long* ion_off, int* flag) {
+    hipLaunchKernelGGL(k_sources_wide, dim3(std::max(1, (n + 255) / 256)), dim3(256), 0, s, reps, r, x, y, z, q,
+                       ion_off, flag);
+    hipLaunchKernelGGL(k_sources_finish, dim3(1), dim3(1), 0, s, reps, r, flag);
 }
 void launch_sort_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* hist) {
     const int tiles = (nsrc + kBuildBlock - 1) / kBuildBlock;

@@ -43,11 +43,13 @@ void launch_sources(hipStream_t s, int nrep, Rep* reps, const int* list, const d
 void launch_sort(hipStream_t s, int nrep, Rep* reps, const int* list);
 void launch_count(hipStream_t s, int nrep, Rep* reps, const int* list);
 // One large replica over a grid of workgroups, with the same results: the sort
-// uses hist (256 * kSortGridMax ints), the count cnt (kCountLevels ints, zero
-// before the call and zero again after it).
+// uses hist (256 * kSortGridMax ints), the count cnt (kCountLevels ints) and the
+// sources flag (one int), both zero before the call and zero again after it.
 constexpr int kSortGridMax = 256;
 constexpr int kCountLevels = 64;
 constexpr int kWideBuildMin = 32768;  // sources from which a single-replica build goes wide
+void launch_sources_wide(hipStream_t s, Rep* reps, int r, int n, const double* x, const double* y,
+                         const double* z, const double* q, const long long* ion_off, int* flag);
 void launch_sort_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* hist);
 void launch_count_wide(hipStream_t s, Rep* reps, int r, int nsrc, int* cnt);
 void launch_leaves_wide(hipStream_t s, Rep* reps, const int* list, int r, int nleaf);
