@@ -535,42 +535,79 @@ k_p2m(Rep* reps, const int* rep_list, int nterms, int mstride) {
     }
 }
 
-// M2M of one level (the launches go deepest level first): with
-// s = c_child - c_parent (every component +-h_child, exact),
-//   M_parent^n = sum_children sum_{k <= n} C(n, k) s^(n-k) M_child^k.
-__global__ void __launch_bounds__(kMomBlock)
+// M2M, one wave per split cell of a level (the launches go deepest level
+// first).  With child d centred at c + s_d,
+// s_d = (+-h/2, +-h/2, +-h/2) (+ on x, y, z where bit 4, 2, 1 of d is set),
+//   M^n = sum_d sum_{k <= n} C(n, k) s_d^{n-k} M_d^k,
+// and s_d^{n-k} = (h/2)^{|n-k|} times the product of the signs of the axes on
+// which n - k is odd.  The wave first combines the eight children of every term
+// k into W_k[e] = sum_d (product over the axes set in e of d's sign) M_d^k (an
+// 8-point Hadamard transform, in LDS), and then each lane forms its terms n as
+//   M^n = sum_{k <= n} C(n, k) (h/2)^{|n-k|} W_k[(n - k) mod 2 per axis]:
+// one read per k instead of eight.
+constexpr int kM2MWaves = 4;
+constexpr int kM2MTerms = (kPMax + 1) * (kPMax + 2) * (kPMax + 3) / 6;
+
+__global__ void __launch_bounds__(64 * kM2MWaves)
 k_m2m(Rep* reps, const int* rep_list, int nterms, int mstride, int level) {
     Rep& R = reps[rep_list ? rep_list[blockIdx.y] : blockIdx.y];
-    if (R.status || level >= R.depth) return;
+    if (R.status || level >= R.depth || nterms > kM2MTerms) return;
+    __shared__ double W[kM2MWaves][8][kM2MTerms];
+    __shared__ double hpow[kM2MWaves][kPMax + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int ls = R.level_start[level], le = R.level_start[level + 1];
-    const long long items = (long long)(le - ls) * nterms;
-    for (long long it = blockIdx.x * (long long)kMomBlock + threadIdx.x; it < items;
-         it += (long long)gridDim.x * kMomBlock) {
-        const int c = ls + (int)(it / nterms), k = (int)(it % nterms);
-        const int first = R.cm[c].y;
-        if (first < 0 || first + 8 > R.ncell) continue;
-        const int n1 = c_mi[3 * k], n2 = c_mi[3 * k + 1], n3 = c_mi[3 * k + 2];
-        const double hc = R.cgeo[c].w * 0.5;
-        double acc = 0.0;
-        for (int d = 0; d < 8; ++d) {
-            const double sx = (d & 4) ? hc : -hc, sy = (d & 2) ? hc : -hc, sz = (d & 1) ? hc : -hc;
-            const double* Mc = R.M + (size_t)(first + d) * mstride;
-            double px = 1.0;
-            for (int k1 = n1; k1 >= 0; --k1) {      // s_x^(n1-k1) grows as k1 falls
-                double py = 1.0;
-                for (int k2 = n2; k2 >= 0; --k2) {
-                    double pz = 1.0;
-                    for (int k3 = n3; k3 >= 0; --k3) {
-                        const double coef = (double)(c_binom[n1][k1] * c_binom[n2][k2] * c_binom[n3][k3]);
-                        acc += coef * (px * py * pz) * Mc[mindex_dev(k1, k2, k3)];
-                        pz *= sz;
-                    }
-                    py *= sy;
-                }
-                px *= sx;
+    for (int base = ls + blockIdx.x * kM2MWaves; base < le; base += gridDim.x * kM2MWaves) {  // uniform
+        const int c = base + w;
+        const int first = c < le ? R.cm[c].y : -1;
+        const bool split = first >= 0 && first + 8 <= R.ncell;
+        if (split) {
+            for (int k = lane; k < nterms; k += 64) {
+                double m[8];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) m[d] = R.M[(size_t)(first + d) * mstride + k];
+#pragma unroll
+                for (int b = 4; b >= 1; b >>= 1)
+#pragma unroll
+                    for (int d = 0; d < 8; ++d)
+                        if (!(d & b)) {
+                            const double lo = m[d], hi = m[d | b];
+                            m[d] = lo + hi;
+                            m[d | b] = hi - lo;
+                        }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) W[w][e][k] = m[e];
+            }
+            if (lane <= kPMax) {
+                const double hc = R.cgeo[c].w * 0.5;
+                double v = 1.0;
+                for (int e = 0; e < lane; ++e) v *= hc;
+                hpow[w][lane] = v;
             }
         }
-        R.M[(size_t)c * mstride + k] = acc;
+        __syncthreads();
+        if (split) {
+            for (int n = lane; n < nterms; n += 64) {
+                const int n1 = c_mi[3 * n], n2 = c_mi[3 * n + 1], n3 = c_mi[3 * n + 2];
+                double acc = 0.0;
+                double b1 = 1.0;  // C(n1, k1)
+                for (int k1 = 0; k1 <= n1; ++k1) {
+                    double b2 = 1.0;
+                    for (int k2 = 0; k2 <= n2; ++k2) {
+                        double b3 = 1.0;
+                        for (int k3 = 0; k3 <= n3; ++k3) {
+                            const int e = (((n1 - k1) & 1) << 2) | (((n2 - k2) & 1) << 1) | ((n3 - k3) & 1);
+                            acc += (b1 * b2 * b3) * hpow[w][(n1 - k1) + (n2 - k2) + (n3 - k3)] *
+                                   W[w][e][mindex_dev(k1, k2, k3)];
+                            b3 = b3 * (double)(n3 - k3) / (double)(k3 + 1);
+                        }
+                        b2 = b2 * (double)(n2 - k2) / (double)(k2 + 1);
+                    }
+                    b1 = b1 * (double)(n1 - k1) / (double)(k1 + 1);
+                }
+                R.M[(size_t)c * mstride + n] = acc;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -666,8 +703,9 @@ void launch_moments(hipStream_t s, int nrep, Rep* reps, const int* list, int nte
             if (level < h.depth)
                 items = std::max(items, (long long)(h.level_start[level + 1] - h.level_start[level]) * nterms);
         }
-        hipLaunchKernelGGL(k_m2m, dim3(chunks(items), nrep), dim3(kMomBlock), 0, s, reps, list, nterms, mstride,
-                           level);
+        const long long cells = items / nterms;
+        const unsigned blocks = (unsigned)std::max(1LL, std::min((cells + kM2MWaves - 1) / kM2MWaves, 8192LL));
+        hipLaunchKernelGGL(k_m2m, dim3(blocks, nrep), dim3(64 * kM2MWaves), 0, s, reps, list, nterms, mstride, level);
     }
     long long cell_items = 0;
     bool any32 = false;
