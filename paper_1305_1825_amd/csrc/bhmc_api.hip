@@ -138,6 +138,8 @@ struct bhmc_tree {
     int* list_rest = nullptr;        // replicas a sweep left unfinished
     std::vector<int> order;          // replicas, largest first (host copy of list_all)
     long long* sweep_add = nullptr;  // n_r per replica
+    int* build_list = nullptr;       // replicas of a build (at most R)
+    long long* build_off = nullptr;  // their first ion in the caller's arrays
     bhmc::MoveIO* io = nullptr;
     double* eterm = nullptr; int eterm_n = 0;
     char* gwork = nullptr; size_t gwork_bytes = 0;  // gradient workspace
@@ -466,11 +468,9 @@ static bhmc_status build_list(bhmc_tree* t, const std::vector<int>& list, const 
                               const double* y, const double* z, const double* q,
                               const std::vector<long long>& ion_off) {
     const int nr = (int)list.size();
-    int* dlist = nullptr;
-    long long* doff = nullptr;
-    HIP_TRY(hipMalloc(&dlist, sizeof(int) * nr));
-    HIP_TRY(hipMalloc(&doff, sizeof(long long) * nr));
-    struct Guard { int* a; long long* b; ~Guard() { hipFree(a); hipFree(b); } } guard{dlist, doff};
+    if (nr < 1 || nr > t->R) return fail(BHMC_EINTERNAL, "build of %d replicas", nr);
+    int* dlist = t->build_list;       // per-handle buffers: no allocation per build
+    long long* doff = t->build_off;
     bhmc_status st = h2d(t, dlist, list.data(), sizeof(int) * nr);
     if (st) return st;
     if (x && (st = h2d(t, doff, ion_off.data(), sizeof(long long) * nr))) return st;
@@ -532,7 +532,7 @@ static void destroy(bhmc_tree* t) {
     for (void* p : t->arena1) if (p) hipFree(p);
     for (void* p : t->arena2) if (p) hipFree(p);
     hipFree(t->reps); hipFree(t->queue); hipFree(t->list_all); hipFree(t->list_one); hipFree(t->list_rest);
-    hipFree(t->sweep_add); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar); hipFree(t->gwork);
+    hipFree(t->sweep_add); hipFree(t->build_list); hipFree(t->build_off); hipFree(t->io); hipFree(t->eterm); hipFree(t->scalar); hipFree(t->gwork);
     hipFree(t->spill); hipFree(t->wide_buf);
     if (t->host) hipHostFree(t->host);
     if (t->pin) hipHostFree(t->pin);
@@ -579,6 +579,8 @@ static bhmc_status create(const bhmc_params* params, int32_t R, const int64_t* n
     if (hipMalloc(&t->list_one, sizeof(int)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "list"));
     if (hipMalloc(&t->list_rest, sizeof(int) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "list"));
     if (hipMalloc(&t->sweep_add, sizeof(long long) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "sweep"));
+    if (hipMalloc(&t->build_list, sizeof(int) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "build list"));
+    if (hipMalloc(&t->build_off, sizeof(long long) * R) != hipSuccess) return bail(fail(BHMC_ENOMEM, "build list"));
     if (hipMalloc(&t->io, sizeof(bhmc::MoveIO)) != hipSuccess) return bail(fail(BHMC_ENOMEM, "io"));
     if (hipMalloc(&t->scalar, sizeof(double) * 4) != hipSuccess) return bail(fail(BHMC_ENOMEM, "scalar"));
     if (ensure_pin(t, 1 << 16) != BHMC_OK) return bail(BHMC_ENOMEM);

@@ -1,4 +1,6 @@
-// Tree construction kernels: one workgroup per replica.
+// Tree construction kernels: one workgroup per replica, or for one large
+// replica a grid of workgroups (the _wide, _hist, _scan, _scatter and _fill
+// forms, with the same results).
 //
 //   k_sources   ions copied in, Kelvin (and line) images made, confinement checked, keys
 //   k_sort      stable LSD radix sort of (key, source) in LDS-ranked tiles
@@ -6,7 +8,7 @@
 //   k_topology  cells level by level (Sec. 3.2 bisection, adaptive by count)
 //   k_leaves    leaf index arrays (pool) and tracking information (Sec. 3.3)
 //   k_p2m       leaf moments M^n = sum q (r - c)^n            (eq. 3.3)
-//   k_m2m       parent moments from children by the binomial shift
+//   k_m2m       parent moments from children by the binomial shift, one wave per cell
 #include "bhmc_dev.hpp"
 #include "bhmc_internal.hpp"
 
@@ -201,35 +203,54 @@ k_sort_hist(const Rep* reps, int r, int pass, int tiles_per_block, int* hist) {
     if (threadIdx.x < 256) hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of m <= 64 * kBuildBlock counts in place, one workgroup: each
-// thread loads its contiguous run of at most 64 counts at once (all loads in
-// flight together), the run sums are scanned in LDS (Hillis-Steele), and each
-// thread writes its run's prefixes.
-constexpr int kScanRun = 64;
+// Exclusive scan of m counts in place, one workgroup, in chunks of 16 counts per
+// thread staged through LDS: each chunk is loaded and stored back with coalesced
+// accesses, each thread scans its 16 consecutive counts (rows padded by one word
+// against bank conflicts), and the thread sums are scanned in LDS (Hillis-Steele)
+// on top of the carry of the chunks before.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kScanPer * kBuildBlock;
+__device__ __forceinline__ int scan_pad(int i) { return i + i / kScanPer; }
+
 __global__ void __launch_bounds__(kBuildBlock) k_sort_scan(int* v, int m) {
+    __shared__ int buf[kScanChunk + kBuildBlock];
     __shared__ int part[2][kBuildBlock];
+    __shared__ int carry;
     const int tid = threadIdx.x;
-    const int per = (m + kBuildBlock - 1) / kBuildBlock;
-    const int lo = std::min(m, tid * per), hi = std::min(m, lo + per);
-    int c[kScanRun];
-#pragma unroll
-    for (int j = 0; j < kScanRun; ++j) c[j] = lo + j < hi ? v[lo + j] : 0;
-    int s = 0;
-#pragma unroll
-    for (int j = 0; j < kScanRun; ++j) s += c[j];
-    int cur = 0;
-    part[0][tid] = s;
+    if (tid == 0) carry = 0;
     __syncthreads();
-    for (int d = 1; d < kBuildBlock; d <<= 1) {
-        part[cur ^ 1][tid] = part[cur][tid] + (tid >= d ? part[cur][tid - d] : 0);
-        cur ^= 1;
+    for (int base = 0; base < m; base += kScanChunk) {  // uniform
+        const int len = std::min(kScanChunk, m - base);
+        for (int k = tid; k < len; k += kBuildBlock) buf[scan_pad(k)] = v[base + k];
         __syncthreads();
-    }
-    int run = part[cur][tid] - s;  // exclusive prefix of this run
+        int c[kScanPer];
+        int s = 0;
 #pragma unroll
-    for (int j = 0; j < kScanRun; ++j) {
-        if (lo + j < hi) v[lo + j] = run;
-        run += c[j];
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = kScanPer * tid + j;
+            c[j] = i < len ? buf[scan_pad(i)] : 0;
+            s += c[j];
+        }
+        int cur = 0;
+        part[0][tid] = s;
+        const int carry0 = carry;
+        __syncthreads();
+        for (int d = 1; d < kBuildBlock; d <<= 1) {
+            part[cur ^ 1][tid] = part[cur][tid] + (tid >= d ? part[cur][tid - d] : 0);
+            cur ^= 1;
+            __syncthreads();
+        }
+        int run = carry0 + part[cur][tid] - s;  // exclusive prefix of this thread's counts
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = kScanPer * tid + j;
+            if (i < len) buf[scan_pad(i)] = run;
+            run += c[j];
+        }
+        __syncthreads();
+        for (int k = tid; k < len; k += kBuildBlock) v[base + k] = buf[scan_pad(k)];
+        if (tid == kBuildBlock - 1) carry = run;  // carry0 plus the chunk's total
+        __syncthreads();
     }
 }
 
