@@ -371,11 +371,15 @@ def run_gradient(theta=0.5, calls=3):
     inf = t.info()
     t.close()
     med = float(np.median(ms))
+    tr = traffic("grad", 1)
     return dict(workload="N=100000 ions + images, shell 10.5<r<120, theta=%.1f, p=6, leaf 16" % theta,
                 ms_per_gradient=med, ms_energy_only=e0.elapsed_time(e1), ratio_to_energy=med / e0.elapsed_time(e1),
                 ms_build=b0.elapsed_time(b1),
                 ions_per_s=len(c["x"]) / (med / 1000.0), E=E, ncell=inf["ncell"],
-                traffic=traffic("grad", 1))
+                traffic=tr,
+                # measured HBM bytes of k_grad over the whole call's time: far below the 8 TB/s
+                # peak, the kernel is bound by its FP64 evaluation of the far cells
+                hbm_gbs=(tr / (med / 1000.0) / 1e9 if tr else None))
 
 
 def run_large(sweeps, grad_each=True):
