@@ -1704,26 +1704,43 @@ __global__ void __launch_bounds__(kMcBlock) k_move(Rep* reps, int r, MoveIO* io)
 
 #include "bhmc_moves.hpp"
 
-// Potential at every ion (targets in groups of kEnergyTargets per
-// workgroup), with the ion and its image excluded, and each ion's term of
+// Potential at every ion, with the ion and its image excluded, and each ion's term of
 //   E / l_B = 1/2 q phi + 1/2 gamma a q^2 / (r^2 - a^2) + Q q / r.
+// A workgroup takes kEnergyTargets consecutive positions of the build's key
+// order (a space-filling curve) and traverses for the ions among them, so that
+// its targets are close in space and share most of their interaction lists.
 __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, double* phi, double* eterm) {
     constexpr int NTG = kEnergyTargets;
     __shared__ Trav<NTG, kEnergyBlock> S;
     __shared__ Rep Rs;
     __shared__ int cnt2[2];
+    __shared__ int s_ion[NTG];
+    __shared__ int s_nv;
     fill_mi(S);
     load_rep(Rs, reps + r);
     __syncthreads();
     const int tid = threadIdx.x;
     const bool imgs = Rs.images != 0;
-    const int ngroups = (Rs.n + NTG - 1) / NTG;
-    // one group of targets per workgroup, or several when the grid is bounded (HBM frontier regions)
+    const int ngroups = (Rs.nsrc + NTG - 1) / NTG;
+    // one group of positions per workgroup, or several when the grid is bounded (HBM frontier regions)
     for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-        const int t0 = grp * NTG;
-        const int nv = min(NTG, Rs.n - t0);
+        const int k0 = grp * NTG;
+        if (tid == 0) {
+            int nv = 0;
+            for (int j = 0; j < NTG && k0 + j < Rs.nsrc; ++j) {
+                const int sid = Rs.perm[k0 + j];
+                if ((unsigned)sid < (unsigned)Rs.n) s_ion[nv++] = sid;
+            }
+            s_nv = nv;
+        }
+        __syncthreads();
+        const int nv = s_nv;
+        if (nv == 0) {  // uniform: only images at these positions
+            __syncthreads();
+            continue;
+        }
         if (tid < nv) {
-            const int ion = t0 + tid;
+            const int ion = s_ion[tid];
             const double4 si = Rs.src[ion];
             const double4 mo = imgs ? Rs.src[Rs.n + ion] : make_double4(0, 0, 0, 0);
             S.tx[tid] = si.x; S.ty[tid] = si.y; S.tz[tid] = si.z;
@@ -1737,7 +1754,7 @@ __global__ void __launch_bounds__(kEnergyBlock) k_energy(Rep* reps, int r, doubl
         __syncthreads();
         traverse<NTG, kEnergyBlock>(Rs, S, nv, cnt2, [](int) {});
         if (tid < nv) {
-            const int ion = t0 + tid;
+            const int ion = s_ion[tid];
             const double4 si = Rs.src[ion];
             const double ph = S.err ? __builtin_nan("") : S.res[tid];
             if (S.err && tid == 0) reps[r].err_detail = S.err;
@@ -2474,7 +2491,9 @@ __global__ void __launch_bounds__(256) k_eline(Rep* reps, int r, double* phi, do
 }
 
 void run_energy(hipStream_t s, Rep* reps, int r, int n, double* phi, double* eterm, int max_grid, int nline) {
-    int grid = (n + kEnergyTargets - 1) / kEnergyTargets;
+    // one workgroup per group of key-order positions: at most (2 + nline) n sources
+    const long long positions = (long long)n * (2 + nline);
+    int grid = (int)std::min<long long>((positions + kEnergyTargets - 1) / kEnergyTargets, 0x7FFFFFFFll);
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
     hipLaunchKernelGGL(k_energy, dim3(grid), dim3(kEnergyBlock), 0, s, reps, r, phi, eterm);
     if (nline > 0) hipLaunchKernelGGL(k_eline, dim3((n + 255) / 256), dim3(256), 0, s, reps, r, phi, eterm);
