@@ -44,11 +44,11 @@ GATED_REPLICAS = dict(theta=0.3, p=5, n0=0)
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by the same
 # counters on a plain device copy), valid only for the sources they were taken on.
 MEASURED_TRAFFIC = {
-    "csrc": "f6aa7616bdbd",
-    "chain": {"units": 100000, "bytes": 183503810},        # eval_p5::k_mcb<512>, 10^5 moves
-    "sweep": {"units": 3038540, "bytes": 1.02028e12},      # eval_p5::k_mcb<512>, one sweep of 256 replicas
-    "sweep_fp32": {"units": 3038540, "bytes": 5.87201e11}, # the same with the single-precision far field
-    "grad": {"units": 1, "bytes": 3.16023e9},              # eval_p6::k_grad, one call at 10^5 ions
+    "csrc": "33b3ffaf2752",
+    "chain": {"units": 100000, "bytes": 183182607},        # eval_p5::k_mcb<512>, 10^5 moves
+    "sweep": {"units": 3038540, "bytes": 1.02800e12},      # eval_p5::k_mcb<512>, one sweep of 256 replicas
+    "sweep_fp32": {"units": 3038540, "bytes": 5.87033e11}, # the same with the single-precision far field
+    "grad": {"units": 1, "bytes": 3.16016e9},              # eval_p6::k_grad, one call at 10^5 ions
 }
 
 
